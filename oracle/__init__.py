@@ -1,0 +1,156 @@
+"""CPU oracle for the queue-driven Bellman-Ford path (test infrastructure).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The product path (the HIP library and
+its Python binding) never does, and this package imports nothing from it: the
+two share no code. Inputs come from ``synth`` only.
+
+Parts and the passages they follow:
+
+- ``bf_rounds``: round-based Bellman-Ford, Alg. 3 on one processing element
+  (relax rule of PARALLEL_RELAX_EDGES, change counter, early exit of
+  Section III.C, negative cycle when the round indexed n-1 still changes).
+- ``bf_fifo``: sequential FIFO Bellman-Ford, the single-thread form of the
+  queue-based solver of Section III.C.
+- ``pred``: smallest-id tight in-neighbour (a fixed choice among equally
+  valid shortest-path trees).
+- ``fifo_run``: the sequential bounded FIFO, the specification the concurrent
+  queue of Section III.A (Alg. 1) is linearizable to.
+- ``history``: checks of concurrent queue histories against that
+  specification (see ``oracle/history.py``).
+
+All values are exact integers; INF = INT64_MAX marks unreached vertices.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+INF = np.iinfo(np.int64).max
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIBDIR = os.path.join(_HERE, "_build")
+_LIB = os.path.join(_LIBDIR, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
+    """Compile the C oracle with gcc into a shared library."""
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(src):
+        return out
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.run(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", tmp, src],
+                   check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def load(path: str | None = None):
+    """Load the oracle library (building it first if it is not there)."""
+    global _lib
+    if path is None and _lib is not None:
+        return _lib
+    with _lock:
+        p = path or _LIB
+        if path is None and not os.path.exists(p):
+            build(force=True)
+        lib = ctypes.CDLL(p)
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        vp = ctypes.c_void_p
+        lib.oracle_bf_rounds.restype = i64
+        lib.oracle_bf_rounds.argtypes = [i32, vp, vp, vp, i32, vp, vp]
+        lib.oracle_bf_fifo.restype = i64
+        lib.oracle_bf_fifo.argtypes = [i32, vp, vp, vp, i32, vp, vp, vp]
+        lib.oracle_pred.restype = None
+        lib.oracle_pred.argtypes = [i32, vp, vp, vp, i32, vp, vp]
+        lib.oracle_fifo_run.restype = i64
+        lib.oracle_fifo_run.argtypes = [i64, i64, vp, vp, vp]
+        if path is None:
+            _lib = lib
+        return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _csr(g):
+    off = np.ascontiguousarray(g.offsets, dtype=np.int64)
+    col = np.ascontiguousarray(g.cols, dtype=np.int32)
+    w = np.ascontiguousarray(g.w, dtype=np.int32)
+    if off.shape[0] != g.n + 1 or off[0] != 0 or off[-1] != col.shape[0]:
+        raise ValueError("malformed CSR")
+    return off, col, w
+
+
+def bf_rounds(g, src: int | None = None, lib=None):
+    """Round-based BF (Alg. 3, one PE). Returns (dist int64[n], neg bool, rounds)."""
+    lib = lib or load()
+    off, col, w = _csr(g)
+    s = g.src if src is None else int(src)
+    d = np.empty(g.n, dtype=np.int64)
+    neg = np.zeros(1, dtype=np.int32)
+    rounds = lib.oracle_bf_rounds(g.n, _ptr(off), _ptr(col), _ptr(w), s, _ptr(d), _ptr(neg))
+    return d, bool(neg[0]), int(rounds)
+
+
+def bf_fifo(g, src: int | None = None, lib=None):
+    """Sequential FIFO BF. Returns (dist, neg, pops, relaxations)."""
+    lib = lib or load()
+    off, col, w = _csr(g)
+    s = g.src if src is None else int(src)
+    d = np.empty(g.n, dtype=np.int64)
+    neg = np.zeros(1, dtype=np.int32)
+    relax = np.zeros(1, dtype=np.int64)
+    pops = lib.oracle_bf_fifo(g.n, _ptr(off), _ptr(col), _ptr(w), s, _ptr(d), _ptr(neg),
+                              _ptr(relax))
+    return d, bool(neg[0]), int(pops), int(relax[0])
+
+
+def pred(g, dist: np.ndarray, src: int | None = None, lib=None) -> np.ndarray:
+    """Smallest-id tight in-neighbour of every reached vertex (-1 for src and
+    unreached vertices)."""
+    lib = lib or load()
+    off, col, w = _csr(g)
+    s = g.src if src is None else int(src)
+    d = np.ascontiguousarray(dist, dtype=np.int64)
+    p = np.empty(g.n, dtype=np.int32)
+    lib.oracle_pred(g.n, _ptr(off), _ptr(col), _ptr(w), s, _ptr(d), _ptr(p))
+    return p
+
+
+def sssp(g, src: int | None = None, method: str = "rounds", lib=None):
+    """Distances, predecessors and the negative-cycle flag for (g, src).
+
+    ``method`` = "rounds" (the authority, Alg. 3) or "fifo" (sequential
+    queue form, much faster on large graphs). On a negative cycle the
+    distances and predecessors are not meaningful and are returned as given.
+    """
+    if method == "rounds":
+        d, neg, _ = bf_rounds(g, src, lib)
+    elif method == "fifo":
+        d, neg, _, _ = bf_fifo(g, src, lib)
+    else:
+        raise ValueError(method)
+    p = pred(g, d, src, lib) if not neg else np.full(g.n, -1, dtype=np.int32)
+    return d, p, neg
+
+
+def fifo_run(capacity: int, ops, lib=None):
+    """Run a sequence of operations on the sequential bounded FIFO.
+
+    ``ops[i] >= 0`` enqueues that value, ``ops[i] < 0`` dequeues once.
+    Returns (ok int8[k], out int64[k] (dequeued value or -1), final size).
+    """
+    lib = lib or load()
+    o = np.ascontiguousarray(ops, dtype=np.int64)
+    res = np.zeros(o.shape[0], dtype=np.int8)
+    out = np.zeros(o.shape[0], dtype=np.int64)
+    size = lib.oracle_fifo_run(int(capacity), o.shape[0], _ptr(o), _ptr(res), _ptr(out))
+    return res, out, int(size)
