@@ -1,0 +1,191 @@
+/*
+ * bq.h - C ABI of the MI355X Broker-Queue / queue-driven Bellman-Ford library
+ * (libbqsssp.so, built for gfx950).
+ *
+ * Two groups of entry points:
+ *
+ *  1. The concurrent FIFO of Section III.A (Alg. 1, the Broker Queue):
+ *     bq_create / bq_destroy / bq_reset (INITIALIZE), bq_enqueue (ENQUEUE,
+ *     Successful or Full), bq_dequeue (DEQUEUE, data or Empty) and
+ *     bq_bench_mixed (the "Global Mixed" scenario of Section IV: even
+ *     workgroups enqueue, odd workgroups dequeue, concurrently).
+ *
+ *  2. Single-source shortest paths with the queue-based Bellman-Ford of
+ *     Section III.C, whose input and output are those of Alg. 3 (graph G,
+ *     source s -> distances d and the negative-cycle detection):
+ *     sssp_ctx_create / sssp_ctx_destroy, sssp_bf (one query) and
+ *     sssp_bf_batched (many queries in one persistent launch).
+ *
+ * Conventions for every call:
+ *  - Pointers named d_* are device pointers (HBM of the current HIP device),
+ *    h_* are host pointers. The caller owns every buffer it passes; the
+ *    library keeps no caller pointer after the call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Every call returns a bq_status; outputs are unspecified unless BQ_OK.
+ *  - Integer arithmetic only: int32 weights, int64 distances.
+ *  - The library never allocates on a solve: queues and workspaces are
+ *    allocated by bq_create / sssp_ctx_create and reused.
+ *  - Calls on one bq_queue or one sssp_ctx must not overlap in time
+ *    (they share its device state); distinct objects are independent.
+ */
+#ifndef BQ_H
+#define BQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BQ_OK = 0,
+    BQ_EINVAL = -1,   /* bad argument: null pointer, size, malformed CSR */
+    BQ_ENOMEM = -2,   /* device or pinned allocation failed */
+    BQ_EHIP = -3,     /* a HIP runtime call failed */
+    BQ_ERANGE = -4,   /* distances cannot be packed: n * max|w| too large */
+    BQ_ETIMEOUT = -5, /* a device-side watchdog fired; state was reset */
+    BQ_EBUSY = -6     /* object too small for this input (max_n / max_m) */
+} bq_status;
+
+/* Opaque handles. */
+typedef struct bq_queue bq_queue;
+typedef struct sssp_ctx sssp_ctx;
+
+/* Launch shape. Zero fields mean "library default". */
+typedef struct {
+    int32_t wg_size;      /* threads per workgroup, multiple of 64 (<= 1024) */
+    int32_t wg_count;     /* workgroups; 0 = fill the chip (occupancy x CUs) */
+    int32_t ticket_batch; /* b: a wave dequeues up to 64*b items per ticket */
+    uint32_t flags;       /* BQ_F_* */
+    uint64_t timeout_us;  /* watchdog for a single wait; 0 = 2 s. A solve
+                             running longer than 10x this is stopped too
+                             (BQ_ETIMEOUT), so no launch runs unbounded. */
+} bq_launch;
+
+#define BQ_F_VALIDATE 1u  /* sssp_bf: check the CSR on the device first */
+
+/* Counters of one bq_bench_mixed run. */
+typedef struct {
+    uint64_t enq_ok, deq_ok;      /* successful operations */
+    uint64_t enq_full, deq_empty; /* attempts that returned Full / Empty and were retried */
+    double ms;                    /* kernel time (HIP events) */
+} bq_bench_stats;
+
+/* Work counters of the last sssp_bf / sssp_bf_batched call on a context. */
+typedef struct {
+    uint64_t dequeued;     /* items taken from the queue */
+    uint64_t relaxations;  /* edges scanned */
+    uint64_t pushes;       /* vertices enqueued after an improvement */
+    uint64_t fanout;       /* row chunks of high-degree vertices enqueued */
+    uint64_t batches;      /* wave dequeue batches */
+    uint64_t walks;        /* parent-pointer walks (negative-cycle search) */
+    uint64_t improvements; /* successful atomicMin lowering a distance */
+    double ms;             /* device time of the call (HIP events) */
+    int32_t grid;          /* workgroups launched */
+    int32_t wg_size;
+} sssp_stats;
+
+/* One query of sssp_bf_batched: all pointers are device pointers. */
+typedef struct {
+    int32_t n;               /* vertices */
+    int32_t src;             /* source vertex */
+    int64_t m;               /* edges */
+    const int64_t* offsets;  /* [n+1] CSR row offsets, offsets[0] = 0, offsets[n] = m */
+    const int32_t* cols;     /* [m] edge targets */
+    const int32_t* w;        /* [m] edge weights */
+    int64_t* dist;           /* [n] out */
+    int32_t* pred;           /* [n] out, may be NULL */
+} sssp_instance;
+
+/* ------------------------------------------------------------------------
+ * Queue (Section III.A, Alg. 1)
+ * ------------------------------------------------------------------------ */
+
+/* INITIALIZE: allocate a queue of `capacity` int32 slots (a power of two,
+ * >= 64) with head = tail = count = 0 and all tickets 0.
+ * `flags` is reserved (pass 0). Returns BQ_EINVAL for a bad capacity,
+ * BQ_ENOMEM if the device allocation fails. */
+bq_status bq_create(uint32_t capacity, uint32_t flags, void* stream, bq_queue** out);
+
+/* Free the queue (synchronizes the device first). NULL is accepted. */
+bq_status bq_destroy(bq_queue* q);
+
+/* INITIALIZE again on `stream` (head = tail = count = 0, tickets and slots
+ * zeroed). Needed after BQ_ETIMEOUT. */
+bq_status bq_reset(bq_queue* q, void* stream);
+
+/* ENQUEUE of n values d_vals[0..n) by a launch of wave-aggregated lanes.
+ * Each value is Successful or Full (Alg. 1); with no concurrent dequeuer the
+ * first min(n, capacity - size) positions taken succeed. *d_n_ok (device,
+ * uint64, overwritten) receives the number of successes. Which values
+ * succeed, and their order in the queue, depend on the schedule, except for
+ * launch->wg_count = 1 and wg_size = 64 (one wave), which enqueues in array
+ * order. launch may be NULL. Synchronous (returns after completion). */
+bq_status bq_enqueue(bq_queue* q, const int32_t* d_vals, uint64_t n, uint64_t* d_n_ok,
+                     const bq_launch* launch, void* stream);
+
+/* DEQUEUE up to n values into d_out[0..*d_n_ok) (compacted; Empty for the
+ * rest). With one wave (see bq_enqueue) the values come out in queue order.
+ * Synchronous. */
+bq_status bq_dequeue(bq_queue* q, int32_t* d_out, uint64_t n, uint64_t* d_n_ok,
+                     const bq_launch* launch, void* stream);
+
+/* Host view of the queue counters (synchronizes the stream). */
+bq_status bq_counters(bq_queue* q, void* stream, uint64_t* h_head, uint64_t* h_tail,
+                      int64_t* h_count);
+
+/* Section IV "Global Mixed": a co-resident grid in which even workgroups
+ * perform n_ops/2 enqueues and odd workgroups n_ops/2 dequeues, each lane
+ * retrying an operation that returned Full/Empty until it succeeds. The
+ * value enqueued by operation i is i. If d_enq_log / d_deq_log are not NULL
+ * (device, int32[n_ops/2] each) the value written at / read from queue
+ * position P - P0 is stored at index P - P0 (P0 = tail before the call), for
+ * checking the position rule, conservation and per-producer order. The
+ * producer of value i is lane (i mod 64) of enqueuer wave ((i / 64) mod W),
+ * W = *h_enq_waves on return. Synchronous. */
+bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
+                         int32_t* d_enq_log, int32_t* d_deq_log, bq_bench_stats* h_out,
+                         int32_t* h_enq_waves, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Queue-based Bellman-Ford SSSP (Section III.C; Alg. 3's inputs/outputs)
+ * ------------------------------------------------------------------------ */
+
+/* Workspace for graphs with n <= max_n and m <= max_m: the vertex queue,
+ * control block and chunk table. Allocated once; calls reuse it. */
+bq_status sssp_ctx_create(int32_t max_n, int64_t max_m, sssp_ctx** out);
+bq_status sssp_ctx_destroy(sssp_ctx* ctx);
+
+/* Single-source shortest paths from src over the CSR graph
+ * (d_offsets int64[n+1], d_cols int32[m], d_w int32[m]).
+ *
+ * Output: d_dist int64[n]: the exact shortest distance, INT64_MAX for
+ * vertices not reachable from src (the paper's infinity);
+ * d_pred int32[n] (may be NULL): the smallest-id in-neighbour u with
+ * dist[u] + w(u,v) == dist[v], -1 for src and unreachable vertices;
+ * *h_neg_cycle: 1 if a negative cycle is reachable from src (then dist and
+ * pred are unspecified), else 0. A negative cycle is a result, not an error.
+ *
+ * Self-loops and parallel edges are allowed. Requires 1 <= n <= max_n,
+ * 0 <= m <= max_m, 0 <= src < n; with BQ_F_VALIDATE the CSR itself is
+ * checked (BQ_EINVAL). BQ_ERANGE when n * max|w| does not fit the packed
+ * 64-bit key (bits for the distance = 62 - ceil(log2(n+1))).
+ * Synchronous: returns when the outputs are final. launch may be NULL. */
+bq_status sssp_bf(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
+                  const int32_t* d_cols, const int32_t* d_w, int32_t src, int64_t* d_dist,
+                  int32_t* d_pred, int32_t* h_neg_cycle, const bq_launch* launch,
+                  void* stream);
+
+/* Work counters and device time of the last call on ctx. */
+bq_status sssp_last_stats(const sssp_ctx* ctx, sssp_stats* h_out);
+
+/* Text for a status code (static storage). */
+const char* bq_strerror(bq_status s);
+
+/* Number of compute units of the current device (for launch sizing). */
+int32_t bq_device_cus(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BQ_H */

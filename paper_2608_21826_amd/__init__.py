@@ -1,0 +1,271 @@
+"""Python binding of libbqsssp.so (the C ABI declared in include/bq.h).
+
+Argument marshalling only: every step of the queue and of the solver runs in
+the library's HIP kernels. PyTorch supplies device memory and streams. If the
+shared library is missing the import of a function fails loudly; there is no
+CPU fallback.
+
+Entry points mirror the C names: ``sssp_bf``, ``Queue`` (bq_create,
+bq_enqueue, bq_dequeue, bq_reset, bq_bench_mixed, bq_counters), ``SsspContext``
+(sssp_ctx_create, sssp_last_stats).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbqsssp.so")
+
+BQ_OK, BQ_EINVAL, BQ_ENOMEM, BQ_EHIP, BQ_ERANGE, BQ_ETIMEOUT, BQ_EBUSY = 0, -1, -2, -3, -4, -5, -6
+BQ_F_VALIDATE = 1
+
+# every symbol include/bq.h declares
+EXPORTS = [
+    "bq_create", "bq_destroy", "bq_reset", "bq_enqueue", "bq_dequeue", "bq_counters",
+    "bq_bench_mixed", "sssp_ctx_create", "sssp_ctx_destroy", "sssp_bf", "sssp_last_stats",
+    "bq_strerror", "bq_device_cus",
+]
+
+
+class BQError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("wg_size", ctypes.c_int32), ("wg_count", ctypes.c_int32),
+                ("ticket_batch", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("timeout_us", ctypes.c_uint64)]
+
+
+class BenchStats(ctypes.Structure):
+    _fields_ = [("enq_ok", ctypes.c_uint64), ("deq_ok", ctypes.c_uint64),
+                ("enq_full", ctypes.c_uint64), ("deq_empty", ctypes.c_uint64),
+                ("ms", ctypes.c_double)]
+
+
+class SsspStats(ctypes.Structure):
+    _fields_ = [("dequeued", ctypes.c_uint64), ("relaxations", ctypes.c_uint64),
+                ("pushes", ctypes.c_uint64), ("fanout", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("walks", ctypes.c_uint64),
+                ("improvements", ctypes.c_uint64), ("ms", ctypes.c_double),
+                ("grid", ctypes.c_int32), ("wg_size", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib(path: str | None = None):
+    """Load libbqsssp.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} not found: build it with __graft_entry__.build() "
+                          "(python -m paper_2608_21826_amd._build)")
+    L = ctypes.CDLL(p)
+    vp, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                              ctypes.c_uint64)
+    P = ctypes.POINTER
+    sig = {
+        "bq_create": ([u32, u32, vp, P(vp)], i32),
+        "bq_destroy": ([vp], i32),
+        "bq_reset": ([vp, vp], i32),
+        "bq_enqueue": ([vp, vp, u64, vp, P(Launch), vp], i32),
+        "bq_dequeue": ([vp, vp, u64, vp, P(Launch), vp], i32),
+        "bq_counters": ([vp, vp, P(u64), P(u64), P(i64)], i32),
+        "bq_bench_mixed": ([vp, u64, P(Launch), vp, vp, P(BenchStats), P(i32), vp], i32),
+        "sssp_ctx_create": ([i32, i64, P(vp)], i32),
+        "sssp_ctx_destroy": ([vp], i32),
+        "sssp_bf": ([vp, i32, i64, vp, vp, vp, i32, vp, vp, P(i32), P(Launch), vp], i32),
+        "sssp_last_stats": ([vp, P(SsspStats)], i32),
+        "bq_strerror": ([i32], ctypes.c_char_p),
+        "bq_device_cus": ([], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    if path is None:
+        _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    try:
+        return lib().bq_strerror(int(status)).decode()
+    except ImportError:
+        return f"status {status}"
+
+
+def _check(status: int, what: str):
+    if status != BQ_OK:
+        raise BQError(status, what)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _launch(launch):
+    if launch is None:
+        return None
+    if isinstance(launch, Launch):
+        return ctypes.byref(launch)
+    return ctypes.byref(Launch(**launch))
+
+
+def _need(t, dtype, name, n=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (ROCm) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+
+
+# ---------------------------------------------------------------------------
+# queue
+# ---------------------------------------------------------------------------
+class Queue:
+    """A Broker Queue of `capacity` int32 slots on the current device."""
+
+    def __init__(self, capacity: int, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().bq_create(capacity, 0, _stream(stream), ctypes.byref(h)), "bq_create")
+        self.handle = h
+        self.capacity = capacity
+
+    def close(self):
+        if self.handle:
+            lib().bq_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+    def reset(self, stream=None):
+        _check(lib().bq_reset(self.handle, _stream(stream)), "bq_reset")
+
+    def enqueue(self, vals, launch=None, stream=None) -> int:
+        import torch
+        _need(vals, torch.int32, "vals")
+        ok = torch.zeros(1, dtype=torch.int64, device=vals.device)
+        _check(lib().bq_enqueue(self.handle, _ptr(vals), vals.numel(), _ptr(ok), _launch(launch),
+                                _stream(stream)), "bq_enqueue")
+        return int(ok.item())
+
+    def dequeue(self, n: int, launch=None, stream=None, device="cuda"):
+        import torch
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        ok = torch.zeros(1, dtype=torch.int64, device=device)
+        _check(lib().bq_dequeue(self.handle, _ptr(out), n, _ptr(ok), _launch(launch),
+                                _stream(stream)), "bq_dequeue")
+        k = int(ok.item())
+        return out[:k]
+
+    def counters(self, stream=None):
+        h, t, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int64()
+        _check(lib().bq_counters(self.handle, _stream(stream), ctypes.byref(h), ctypes.byref(t),
+                                 ctypes.byref(c)), "bq_counters")
+        return h.value, t.value, c.value
+
+    def bench_mixed(self, n_ops: int, launch=None, log: bool = False, stream=None,
+                    device="cuda"):
+        """Section IV "Global Mixed" run; returns (stats dict, enq_log, deq_log)."""
+        import torch
+        el = dl = None
+        if log:
+            el = torch.full((n_ops // 2,), -1, dtype=torch.int32, device=device)
+            dl = torch.full((n_ops // 2,), -1, dtype=torch.int32, device=device)
+        st = BenchStats()
+        w = ctypes.c_int32()
+        _check(lib().bq_bench_mixed(self.handle, n_ops, _launch(launch), _ptr(el), _ptr(dl),
+                                    ctypes.byref(st), ctypes.byref(w), _stream(stream)),
+               "bq_bench_mixed")
+        d = {k: getattr(st, k) for k, _ in st._fields_}
+        d["enq_waves"] = w.value
+        return d, el, dl
+
+
+# ---------------------------------------------------------------------------
+# SSSP
+# ---------------------------------------------------------------------------
+class SsspContext:
+    """Workspace for graphs up to max_n vertices and max_m edges."""
+
+    def __init__(self, max_n: int, max_m: int):
+        h = ctypes.c_void_p()
+        _check(lib().sssp_ctx_create(int(max_n), int(max_m), ctypes.byref(h)), "sssp_ctx_create")
+        self.handle = h
+        self.max_n, self.max_m = int(max_n), int(max_m)
+
+    def close(self):
+        if self.handle:
+            lib().sssp_ctx_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+    def solve(self, offsets, cols, w, src: int, dist=None, pred=None, want_pred=True,
+              launch=None, validate=False, stream=None):
+        """sssp_bf on device tensors; returns (dist int64, pred int32 or None, neg bool)."""
+        import torch
+        n = offsets.numel() - 1
+        m = cols.numel()
+        _need(offsets, torch.int64, "offsets", n + 1)
+        _need(cols, torch.int32, "cols")
+        _need(w, torch.int32, "w", m)
+        dev = offsets.device
+        if dist is None:
+            dist = torch.empty(n, dtype=torch.int64, device=dev)
+        _need(dist, torch.int64, "dist", n)
+        if want_pred and pred is None:
+            pred = torch.empty(n, dtype=torch.int32, device=dev)
+        if pred is not None:
+            _need(pred, torch.int32, "pred", n)
+        L = launch
+        if validate:
+            L = Launch(**(launch or {})) if not isinstance(launch, Launch) else launch
+            L.flags |= BQ_F_VALIDATE
+        neg = ctypes.c_int32(0)
+        _check(lib().sssp_bf(self.handle, n, m, _ptr(offsets), _ptr(cols), _ptr(w), int(src),
+                             _ptr(dist), _ptr(pred), ctypes.byref(neg), _launch(L),
+                             _stream(stream)), "sssp_bf")
+        return dist, pred, bool(neg.value)
+
+    def stats(self) -> dict:
+        s = SsspStats()
+        _check(lib().sssp_last_stats(self.handle, ctypes.byref(s)), "sssp_last_stats")
+        return s.as_dict()
+
+
+def sssp_bf(offsets, cols, w, src: int, want_pred=True, launch=None, validate=True, ctx=None):
+    """One SSSP query on device tensors (allocates a context if none given)."""
+    own = ctx is None
+    if own:
+        ctx = SsspContext(offsets.numel() - 1, cols.numel())
+    try:
+        return ctx.solve(offsets, cols, w, src, want_pred=want_pred, launch=launch,
+                         validate=validate)
+    finally:
+        if own:
+            ctx.close()
+
+
+def device_cus() -> int:
+    return int(lib().bq_device_cus())

@@ -1,0 +1,149 @@
+"""GPU checks of the Broker Queue through the C ABI.
+
+- One wave = a sequential client: an interleaved sequence of bulk enqueues
+  and dequeues must reproduce the sequential FIFO oracle exactly (values,
+  order, Full/Empty counts), also with tiny capacities (many ticket rounds).
+- Many waves: counts are fixed by the FIFO specification (min(n, free)),
+  and the multiset is conserved.
+- The Section IV "Global Mixed" run: position rule, conservation,
+  per-producer FIFO and quiescent counters, from full position logs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import history
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2608_21826_amd")
+
+ONE_WAVE = {"wg_size": 64, "wg_count": 1}
+
+
+@pytest.mark.parametrize("cap", [64, 128, 1024])
+@pytest.mark.parametrize("seed", range(4))
+def test_one_wave_matches_sequential_fifo(cap, seed):
+    print(f"[queue] one-wave cap={cap} seed={seed}", flush=True)
+    rng = np.random.default_rng(seed)
+    q = pkg.Queue(cap)
+    ops = []          # oracle op list
+    got_ok, got_out = [], []
+    nxt = 0
+    for step in range(40):
+        if rng.random() < 0.55:
+            k = int(rng.integers(0, 3 * cap // 2))
+            vals = np.arange(nxt, nxt + k, dtype=np.int32)
+            nxt += k
+            ok = q.enqueue(torch.from_numpy(vals).cuda(), launch=ONE_WAVE) if k else 0
+            ops.extend(vals.tolist())
+            got_ok.append(("e", k, ok))
+        else:
+            k = int(rng.integers(0, 3 * cap // 2))
+            out = q.dequeue(k, launch=ONE_WAVE).cpu().numpy() if k else np.zeros(0, np.int32)
+            ops.extend([-1] * k)
+            got_ok.append(("d", k, out))
+    res, out, size = oracle.fifo_run(cap, np.array(ops, dtype=np.int64))
+    i = 0
+    for kind, k, val in got_ok:
+        r = res[i:i + k]
+        if kind == "e":
+            assert val == int(r.sum())
+            # a one-wave bulk enqueue succeeds for a prefix of the array
+            assert np.all(r[:val] == 1) and np.all(r[val:] == 0)
+        else:
+            exp = out[i:i + k][r == 1]
+            assert np.array_equal(val, exp)
+        i += k
+    h, t, c = q.counters()
+    assert t - h == size == c
+    q.close()
+
+
+@pytest.mark.parametrize("cap", [64, 4096, 1 << 16])
+def test_many_waves_counts_and_conservation(cap):
+    """Success counts follow the FIFO specification exactly; every value that
+    comes out went in (with multiplicity), and everything that went in comes
+    out by the end."""
+    import collections
+    print(f"[queue] many-waves cap={cap}", flush=True)
+    q = pkg.Queue(cap)
+    rng = np.random.default_rng(cap)
+    size = 0
+    offered = collections.Counter()
+    taken = collections.Counter()
+    n_in = 0
+    nxt = 0
+    for rep in range(6):
+        n = int(rng.integers(1, 3 * cap))
+        vals = np.arange(nxt, nxt + n, dtype=np.int32)
+        nxt += n
+        ok = q.enqueue(torch.from_numpy(vals).cuda())
+        assert ok == min(n, cap - size)
+        offered.update(vals.tolist())
+        size += ok
+        n_in += ok
+        h, t, c = q.counters()
+        assert t - h == c == size
+        k = int(rng.integers(1, 2 * cap))
+        out = q.dequeue(k).cpu().numpy()
+        assert out.size == min(k, size)
+        size -= out.size
+        taken.update(out.tolist())
+    out = q.dequeue(4 * cap).cpu().numpy()
+    taken.update(out.tolist())
+    h, t, c = q.counters()
+    assert c == 0 and t == h
+    assert sum(taken.values()) == n_in
+    assert all(v == 1 for v in taken.values())
+    assert all(offered[k] >= 1 for k in taken)
+    q.close()
+
+
+def test_many_waves_exact_multiset():
+    q = pkg.Queue(1 << 14)
+    vals = np.random.default_rng(1).permutation(10000).astype(np.int32)
+    assert q.enqueue(torch.from_numpy(vals).cuda()) == 10000
+    out = q.dequeue(20000).cpu().numpy()
+    history.check_conservation(vals, out, np.zeros(0))
+    q.close()
+
+
+def _mixed(cap, n_ops, launch=None):
+    print(f"[queue] mixed cap={cap} n_ops={n_ops} launch={launch}", flush=True)
+    q = pkg.Queue(cap)
+    st, el, dl = q.bench_mixed(n_ops, launch=launch, log=True)
+    torch.cuda.synchronize()
+    half = n_ops // 2
+    assert st["enq_ok"] == half and st["deq_ok"] == half
+    el, dl = el.cpu().numpy(), dl.cpu().numpy()
+    history.check_positions(el, dl, half)
+    history.check_conservation(np.arange(half), dl, np.zeros(0))
+    # producer of value i: lane i % 64 of enqueuer wave (i // 64) % W; its
+    # sequence number is i // (64 W). Recode values as (producer, seq).
+    W = st["enq_waves"]
+    i = el.astype(np.int64)
+    prod = ((i // 64) % W) * 64 + (i % 64)
+    seq = i // (64 * W)
+    history.check_producer_fifo((prod << 20) | seq, 20)
+    h, t, c = q.counters()
+    history.check_quiescent(h, t, c, cap)
+    q.close()
+    return st
+
+
+@pytest.mark.parametrize("cap", [64, 256, 4096, 1 << 20])
+def test_mixed_small(cap):
+    _mixed(cap, 1 << 20)
+
+
+@pytest.mark.parametrize("wgs,wgsize", [(2, 64), (8, 256), (64, 512)])
+def test_mixed_shapes(wgs, wgsize):
+    _mixed(1024, 1 << 18, {"wg_count": wgs, "wg_size": wgsize})
+
+
+def test_mixed_full_size():
+    """The measured configuration: 2^20 slots, 2^26 operations."""
+    st = _mixed(1 << 20, 1 << 26)
+    print(f"[queue] full mixed {st}", flush=True)
