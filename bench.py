@@ -1,0 +1,247 @@
+"""Benchmark of the hot path on one MI355X.
+
+One step = one pass over the whole path for the measured workload: the
+Section IV "Global Mixed" queue run (2^20 int32 slots, 2^26 operations,
+even workgroups enqueue, odd workgroups dequeue) followed by one
+queue-driven Bellman-Ford solve (init, persistent solver, unpack of
+distances and predecessors) on the RMAT scale-20 graph (16.8M edges,
+potential-shifted int32 weights) from its highest-degree vertex.
+
+Prints one JSON line. `value` is SSSP GTEPS (reached edges / device time of
+the solve, the Graph500 convention); queue Mops/s is reported beside it.
+Inputs are resident in HBM before the timed region starts.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--calib]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
+QUEUE_CAP = 1 << 20
+QUEUE_OPS = 1 << 26
+# algorithmic bytes per unit of work (per dequeued item: row offsets 16 B,
+# key RMW 8 B, slot 4 B, ticket read+write 8 B, queue bookkeeping 4 B; per
+# scanned edge: col 4 B + weight 4 B + 8 B key atomic; per enqueue: slot 4 B,
+# ticket 8 B, key already counted with the edge, 4 B bookkeeping)
+BYTES_PER_DEQ = 40
+BYTES_PER_EDGE = 16
+BYTES_PER_PUSH = 16
+PMC_FILE = os.path.join(ROOT, "profiles", "sssp_rmat20_pmc.txt")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("bq_device.hpp", "sssp.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2608_21826_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(per_launch_units):
+    """HBM bytes per solver launch from the committed counter summary, or
+    None when it is missing or was taken on other kernel sources."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    rec = {}
+    for line in open(PMC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(g, m_reached, budget_s=12.0):
+    """The oracle as it stands (round-based Bellman-Ford, Alg. 3 on one
+    processing element, single thread) on the same graph and source, repeated
+    until about budget_s of CPU time."""
+    import oracle
+    oracle.load()
+    times = []
+    t_all = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        _, neg, rounds = oracle.bf_rounds(g)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_all > budget_s or len(times) >= 30:
+            break
+    t = float(np.mean(times))
+    return {"value": m_reached / t / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"{len(times)} full solves of the measured RMAT-20 query with the "
+                      f"round-based oracle ({rounds} rounds each, mean {t * 1e3:.0f} ms); the "
+                      f"queue leg is not timed on the CPU"}
+
+
+def run_probes(pkg, torch, dev):
+    """Measured peaks of the resources the solver uses (context for the
+    roofline; the reported peak stays the published HBM figure)."""
+    cus = pkg.device_cus()
+    res = {"cus": cus}
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 8, dtype=torch.int64, device=dev)
+    b = torch.empty_like(a)
+    pkg.probe(0, a, b, size=nbytes, grid=8 * cus, block=256)
+    ms = min(pkg.probe(0, a, b, size=nbytes, grid=8 * cus, block=256) for _ in range(5))
+    res["hbm_copy_GBs"] = round(2 * nbytes / ms / 1e6, 1)
+    del a, b
+    sink = torch.zeros(2, dtype=torch.int64, device=dev)
+    for words, name in ((1 << 20, "8MiB"), (1 << 25, "256MiB")):
+        t = torch.full((words,), 2**62, dtype=torch.int64, device=dev)
+        grid, block, opl = 8 * cus, 256, 64
+        pkg.probe(1, t, sink, size=words, ops_per_lane=opl, grid=grid, block=block)
+        ms = min(pkg.probe(1, t, sink, size=words, ops_per_lane=opl, grid=grid, block=block)
+                 for _ in range(3))
+        res[f"atomic_min_rand_{name}_Gops"] = round(grid * block * opl / ms / 1e6, 2)
+        del t
+    word = torch.zeros(2, dtype=torch.int64, device=dev)
+    grid, block, opl = 4 * cus, 256, 8
+    pkg.probe(2, word, None, ops_per_lane=opl, grid=grid, block=block)
+    ms = min(pkg.probe(2, word, None, ops_per_lane=opl, grid=grid, block=block) for _ in range(3))
+    res["atomic_add_one_word_Mops"] = round(grid * block * opl / ms / 1e3, 1)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run a 1 GiB copy kernel (byte-counter calibration)")
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--sssp-only", action="store_true",
+                    help="skip the queue leg (for counter passes on the solver kernel)")
+    ap.add_argument("--probes", action="store_true",
+                    help="measure HBM copy and atomic rates (roofline context)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU form of "
+              "this path is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2608_21826_amd as pkg
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    g = synth.rmat(args.scale)
+    log(f"graph rmat{args.scale}: n={g.n} m={g.m} src={g.src} ({time.time() - t0:.1f}s)")
+    off = torch.from_numpy(g.offsets).to(dev)
+    col = torch.from_numpy(g.cols).to(dev)
+    w = torch.from_numpy(g.w).to(dev)
+    ctx = pkg.SsspContext(g.n, g.m)
+    q = pkg.Queue(QUEUE_CAP)
+    dist = torch.empty(g.n, dtype=torch.int64, device=dev)
+    pred = torch.empty(g.n, dtype=torch.int32, device=dev)
+
+    # once, outside the timed region: validate the CSR and count reached edges
+    ctx.solve(off, col, w, g.src, dist=dist, pred=pred, validate=True)
+    reached = (dist != np.iinfo(np.int64).max).cpu().numpy()
+    deg = np.diff(g.offsets)
+    m_reached = int(deg[reached].sum())
+    log(f"reached {int(reached.sum())} vertices, {m_reached} edges")
+
+    if args.calib:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 8, dtype=torch.int64, device=dev)
+        b = torch.empty_like(a)
+        ms = pkg.probe(0, a, b, size=nbytes, grid=8 * pkg.device_cus(), block=256)
+        log(f"calibration copy {nbytes} B in {ms:.3f} ms = {2 * nbytes / ms / 1e6:.0f} GB/s")
+        del a, b
+
+    probes = None
+    if args.probes:
+        probes = run_probes(pkg, torch, dev)
+        log(f"probes {probes}")
+
+    def step():
+        st = {"ms": float("nan"), "enq_full": 0, "deq_empty": 0}
+        if not args.sssp_only:
+            st, _, _ = q.bench_mixed(QUEUE_OPS)
+        ctx.solve(off, col, w, g.src, dist=dist, pred=pred)
+        return st, ctx.stats()
+
+    for i in range(args.warmup):
+        step()
+    log(f"warmup {args.warmup} done")
+    torch.cuda.synchronize()
+    qs, ss = [], []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        a_, b_ = step()
+        qs.append(a_)
+        ss.append(b_)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    log(f"timed {args.steps} steps in {wall:.3f}s")
+
+    q_ms = np.array([x["ms"] for x in qs])
+    s_ms = np.array([x["ms"] for x in ss])
+    k_ms = np.array([x["solve_ms"] for x in ss])
+    gteps = m_reached / (s_ms.mean() * 1e-3) / 1e9
+    qmops = QUEUE_OPS / (q_ms.mean() * 1e-3) / 1e6
+    deq = float(np.mean([x["dequeued"] for x in ss]))
+    rel = float(np.mean([x["relaxations"] for x in ss]))
+    push = float(np.mean([x["pushes"] for x in ss]))
+    alg_bytes = BYTES_PER_DEQ * deq + BYTES_PER_EDGE * rel + BYTES_PER_PUSH * push
+    achieved = alg_bytes / (k_ms.mean() * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": read_traffic(None), "kernel": "k_solve<64>",
+            "algorithmic_bytes_per_launch": int(alg_bytes),
+            "kernel_ms": round(float(k_ms.mean()), 4)}
+    out = {
+        "metric": "SSSP GTEPS + queue Mops/s on 1 MI355X; batched/served vs one-at-a-time",
+        "value": round(gteps, 4), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": f"rmat{args.scale}_sssp+queue_mixed", "n": g.n, "m": g.m,
+                   "src": g.src, "m_reached": m_reached, "queue_capacity": QUEUE_CAP,
+                   "queue_ops": QUEUE_OPS, "parallelism": "single_gpu"},
+        "queue_mops": round(qmops, 2),
+        "sssp": {"ms": round(float(s_ms.mean()), 4), "ms_median": round(float(np.median(s_ms)), 4),
+                 "solver_kernel_ms": round(float(k_ms.mean()), 4),
+                 "relaxations": int(rel), "dequeued": int(deq), "pushes": int(push),
+                 "work_ratio_k": round(rel / m_reached, 3),
+                 "relax_per_s_G": round(rel / (k_ms.mean() * 1e-3) / 1e9, 3),
+                 "grid": int(ss[-1]["grid"])},
+        "queue": {"ms": round(float(q_ms.mean()), 4), "enq_full": int(qs[-1]["enq_full"]),
+                  "deq_empty": int(qs[-1]["deq_empty"])},
+        "roofline": roof,
+    }
+    if probes:
+        out["probes"] = probes
+        if probes.get("atomic_min_rand_8MiB_Gops"):
+            out["atomic_frac"] = round(
+                (rel / (k_ms.mean() * 1e-3) / 1e9) / probes["atomic_min_rand_8MiB_Gops"], 4)
+    if not args.no_cpu:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(g, m_reached)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -81,6 +81,7 @@ typedef struct {
     uint64_t walks;        /* parent-pointer walks (negative-cycle search) */
     uint64_t improvements; /* successful atomicMin lowering a distance */
     double ms;             /* device time of the call (HIP events) */
+    double solve_ms;       /* the persistent solver kernel alone (HIP events) */
     int32_t grid;          /* workgroups launched */
     int32_t wg_size;
 } sssp_stats;
@@ -178,6 +179,23 @@ bq_status sssp_bf(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
 
 /* Work counters and device time of the last call on ctx. */
 bq_status sssp_last_stats(const sssp_ctx* ctx, sssp_stats* h_out);
+
+/* ------------------------------------------------------------------------
+ * Roofline probes (measurement only)
+ * ------------------------------------------------------------------------ */
+
+/* Time one probe kernel with HIP events on `stream` (synchronous):
+ *  kind 0: stream copy of `size` bytes (multiple of 16) from d_a to d_b -
+ *          the HBM bandwidth probe and the calibration kernel for byte
+ *          counters;
+ *  kind 1: grid*block lanes each do ops_per_lane (multiple of 4) returning
+ *          64-bit atomicMin at random slots of the int64 table d_a of `size`
+ *          words (power of two); d_b: 8 bytes of scratch;
+ *  kind 2: grid*block lanes each do ops_per_lane atomicAdd on the single
+ *          uint64 d_a[0] (16 bytes needed).
+ * *h_ms receives the kernel time. */
+bq_status bq_probe(int32_t kind, void* d_a, void* d_b, uint64_t size, uint64_t ops_per_lane,
+                   int32_t grid, int32_t block, double* h_ms, void* stream);
 
 /* Text for a status code (static storage). */
 const char* bq_strerror(bq_status s);

@@ -24,7 +24,7 @@ BQ_F_VALIDATE = 1
 EXPORTS = [
     "bq_create", "bq_destroy", "bq_reset", "bq_enqueue", "bq_dequeue", "bq_counters",
     "bq_bench_mixed", "sssp_ctx_create", "sssp_ctx_destroy", "sssp_bf", "sssp_last_stats",
-    "bq_strerror", "bq_device_cus",
+    "bq_strerror", "bq_device_cus", "bq_probe",
 ]
 
 
@@ -51,7 +51,8 @@ class SsspStats(ctypes.Structure):
                 ("pushes", ctypes.c_uint64), ("fanout", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("walks", ctypes.c_uint64),
                 ("improvements", ctypes.c_uint64), ("ms", ctypes.c_double),
-                ("grid", ctypes.c_int32), ("wg_size", ctypes.c_int32)]
+                ("solve_ms", ctypes.c_double), ("grid", ctypes.c_int32),
+                ("wg_size", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -87,6 +88,7 @@ def lib(path: str | None = None):
         "sssp_last_stats": ([vp, P(SsspStats)], i32),
         "bq_strerror": ([i32], ctypes.c_char_p),
         "bq_device_cus": ([], i32),
+        "bq_probe": ([i32, vp, vp, u64, u64, i32, i32, P(ctypes.c_double), vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -269,3 +271,12 @@ def sssp_bf(offsets, cols, w, src: int, want_pred=True, launch=None, validate=Tr
 
 def device_cus() -> int:
     return int(lib().bq_device_cus())
+
+
+def probe(kind: int, a, b=None, size: int = 0, ops_per_lane: int = 0, grid: int = 1024,
+          block: int = 256, stream=None) -> float:
+    """Run one roofline probe kernel (see bq_probe in include/bq.h); returns ms."""
+    ms = ctypes.c_double()
+    _check(lib().bq_probe(int(kind), _ptr(a), _ptr(b), int(size), int(ops_per_lane), int(grid),
+                          int(block), ctypes.byref(ms), _stream(stream)), "bq_probe")
+    return ms.value

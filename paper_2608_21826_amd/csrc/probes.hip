@@ -1,0 +1,100 @@
+// Roofline probes for the two resources the queue-driven solver uses:
+// HBM bandwidth (a streaming copy, also the calibration kernel for the HBM
+// byte counters) and the device's 64-bit atomic rate (random atomicMin over
+// a table, and atomicAdd on a single contended word).
+#include <hip/hip_runtime.h>
+
+#include "host_common.hpp"
+
+namespace {
+
+__global__ void k_probe_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                             unsigned long long n16) {
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+         i += stride)
+        dst[i] = src[i];
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
+    // SplitMix64 finalizer
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// ops_per_lane returning 64-bit atomicMins at uniformly random slots of a
+// table of 2^log_slots words
+__global__ void k_probe_atomic_min(long long* table, unsigned log_slots,
+                                   unsigned long long ops_per_lane, unsigned long long seed,
+                                   unsigned long long* sink) {
+    const unsigned long long tid = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long mask = (1ull << log_slots) - 1ull;
+    long long acc = 0;
+    for (unsigned long long i = 0; i < ops_per_lane; i += 4) {
+        long long o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const unsigned long long h = mix64(seed ^ (tid * 0x100000001B3ull + i + r));
+            o[r] = __hip_atomic_fetch_min(&table[h & mask], (long long)(h >> 20), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        }
+        acc += o[0] ^ o[1] ^ o[2] ^ o[3];
+    }
+    if (acc == 0x123456789ll) sink[0] = 1;  // keep the results live
+}
+
+// every lane: ops_per_lane atomicAdds on one word (fully contended)
+__global__ void k_probe_atomic_add1(unsigned long long* word, unsigned long long ops_per_lane) {
+    unsigned long long acc = 0;
+    for (unsigned long long i = 0; i < ops_per_lane; ++i)
+        acc += __hip_atomic_fetch_add(word, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (acc == 1ull) word[1] = acc;
+}
+
+}  // namespace
+
+extern "C" {
+
+bq_status bq_probe(int32_t kind, void* d_a, void* d_b, uint64_t size, uint64_t ops_per_lane,
+                   int32_t grid, int32_t block, double* h_ms, void* stream) {
+    if (!d_a || !h_ms || grid < 1 || block < 64 || block > 1024) return BQ_EINVAL;
+    hipStream_t s = bqh::as_stream(stream);
+    hipEvent_t e0, e1;
+    BQ_HIP_TRY(hipEventCreate(&e0));
+    BQ_HIP_TRY(hipEventCreate(&e1));
+    BQ_HIP_TRY(hipEventRecord(e0, s));
+    switch (kind) {
+        case 0:  // copy size bytes from d_a to d_b (size multiple of 16)
+            if (!d_b || (size & 15ull)) return BQ_EINVAL;
+            hipLaunchKernelGGL(k_probe_copy, dim3(grid), dim3(block), 0, s, (const uint4*)d_a,
+                               (uint4*)d_b, (unsigned long long)(size / 16ull));
+            break;
+        case 1: {  // random atomicMin over a table of size (power of two) words
+            if (!d_b || size < 2 || (size & (size - 1))) return BQ_EINVAL;
+            unsigned lg = bqh::log2_exact(size);
+            hipLaunchKernelGGL(k_probe_atomic_min, dim3(grid), dim3(block), 0, s, (long long*)d_a,
+                               lg, (unsigned long long)ops_per_lane, 0x5EEDull,
+                               (unsigned long long*)d_b);
+            break;
+        }
+        case 2:  // single contended word (needs 2 words of space)
+            hipLaunchKernelGGL(k_probe_atomic_add1, dim3(grid), dim3(block), 0, s,
+                               (unsigned long long*)d_a, (unsigned long long)ops_per_lane);
+            break;
+        default:
+            return BQ_EINVAL;
+    }
+    BQ_HIP_TRY(hipGetLastError());
+    BQ_HIP_TRY(hipEventRecord(e1, s));
+    BQ_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    BQ_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    *h_ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return BQ_OK;
+}
+
+}  // extern "C"

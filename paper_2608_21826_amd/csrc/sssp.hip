@@ -602,7 +602,7 @@ struct sssp_ctx {
     unsigned* chunk_owner;
     unsigned chunk_log;
     bq::Ctrl* h_ctrl;  // pinned copy of the control block
-    hipEvent_t ev0, ev1;
+    hipEvent_t ev0, ev1, evs0, evs1;
     bool dirty;        // queue state must be rebuilt before the next solve
     sssp_stats last;
     int solve_per_cu[3];
@@ -697,6 +697,8 @@ bq_status sssp_ctx_create(int32_t max_n, int64_t max_m, sssp_ctx** out) {
     }
     BQ_HIP_TRY(hipEventCreate(&c->ev0));
     BQ_HIP_TRY(hipEventCreate(&c->ev1));
+    BQ_HIP_TRY(hipEventCreate(&c->evs0));
+    BQ_HIP_TRY(hipEventCreate(&c->evs1));
     bq_status st = ctx_reset_queue(c, nullptr);
     if (st != BQ_OK) {
         sssp_ctx_destroy(c);
@@ -717,6 +719,8 @@ bq_status sssp_ctx_destroy(sssp_ctx* c) {
     if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->evs0) (void)hipEventDestroy(c->evs0);
+    if (c->evs1) (void)hipEventDestroy(c->evs1);
     free(c);
     return BQ_OK;
 }
@@ -782,12 +786,14 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     BQ_HIP_TRY(hipGetLastError());
     int grid = 0;
     bq_status st;
+    BQ_HIP_TRY(hipEventRecord(c->evs0, s));
     switch (L.batch) {
         case 1: st = launch_solve<64>(c, a, L, s, 0, &grid); break;
         case 2: st = launch_solve<128>(c, a, L, s, 1, &grid); break;
         default: st = launch_solve<256>(c, a, L, s, 2, &grid); break;
     }
     if (st != BQ_OK) return st;
+    BQ_HIP_TRY(hipEventRecord(c->evs1, s));
     hipLaunchKernelGGL(k_unpack, dim3(grid_for(n)), dim3(256), 0, s, (long long*)d_dist,
                        (int*)d_pred, n, src, shift);
     BQ_HIP_TRY(hipGetLastError());
@@ -795,8 +801,9 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     BQ_HIP_TRY(hipMemcpyAsync(c->h_ctrl, c->ctrl, sizeof(bq::Ctrl), hipMemcpyDeviceToHost, s));
     BQ_HIP_TRY(hipStreamSynchronize(s));
     const bq::Ctrl* h = c->h_ctrl;
-    float ms = 0.f;
+    float ms = 0.f, sms = 0.f;
     BQ_HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    BQ_HIP_TRY(hipEventElapsedTime(&sms, c->evs0, c->evs1));
     c->last.dequeued = h->stats[bq::ST_DEQ].v;
     c->last.relaxations = h->stats[bq::ST_RELAX].v;
     c->last.pushes = h->stats[bq::ST_PUSH].v;
@@ -805,6 +812,7 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     c->last.walks = h->stats[bq::ST_WALK].v;
     c->last.improvements = h->stats[bq::ST_IMPROVE].v;
     c->last.ms = ms;
+    c->last.solve_ms = sms;
     c->last.grid = grid;
     c->last.wg_size = SOLVE_WG;
     const unsigned long long err = h->error.v;
