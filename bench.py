@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="also run a 1 GiB copy kernel (byte-counter calibration)")
     ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="library default launch shapes (no autotuning)")
     ap.add_argument("--sssp-only", action="store_true",
                     help="skip the queue leg (for counter passes on the solver kernel)")
     ap.add_argument("--probes", action="store_true",
@@ -176,11 +178,37 @@ def main():
         probes = run_probes(pkg, torch, dev)
         log(f"probes {probes}")
 
+    # launch shapes, chosen before the timed region: the library's autotuner
+    # for the solver, a small search over ticket batch / grid for the queue
+    sssp_launch = {}
+    if not args.no_tune:
+        sssp_launch, tune_ms = ctx.autotune(off, col, w, g.src, reps=2)
+        log(f"sssp autotune: {sssp_launch} {tune_ms:.3f} ms")
+    queue_launch = {"ticket_batch": 1}
+    queue_b1_ms = None
+    if not args.sssp_only:
+        best = None
+        for b in (1, 4, 16, 64):
+            for wgsz in (256, 1024):
+                for wgs in (64, 256, 0):
+                    L = {"ticket_batch": b, "wg_size": wgsz, "wg_count": wgs}
+                    t = min(q.bench_mixed(QUEUE_OPS, launch=L)[0]["ms"] for _ in range(2))
+                    if b == 1 and (queue_b1_ms is None or t < queue_b1_ms):
+                        queue_b1_ms = t
+                    if best is None or t < best[0]:
+                        best = (t, L)
+                if args.no_tune:
+                    break
+            if args.no_tune:
+                break
+        queue_launch = best[1]
+        log(f"queue launch: {queue_launch} {best[0]:.3f} ms (b=1 best {queue_b1_ms:.3f} ms)")
+
     def step():
         st = {"ms": float("nan"), "enq_full": 0, "deq_empty": 0}
         if not args.sssp_only:
-            st, _, _ = q.bench_mixed(QUEUE_OPS)
-        ctx.solve(off, col, w, g.src, dist=dist, pred=pred)
+            st, _, _ = q.bench_mixed(QUEUE_OPS, launch=queue_launch)
+        ctx.solve(off, col, w, g.src, dist=dist, pred=pred, launch=sssp_launch or None)
         return st, ctx.stats()
 
     for i in range(args.warmup):
@@ -222,9 +250,13 @@ def main():
                    "src": g.src, "m_reached": m_reached, "queue_capacity": QUEUE_CAP,
                    "queue_ops": QUEUE_OPS, "parallelism": "single_gpu"},
         "queue_mops": round(qmops, 2),
+        "queue_mops_b1": round(QUEUE_OPS / (queue_b1_ms * 1e-3) / 1e6, 2) if queue_b1_ms else None,
+        "launch": {"sssp": sssp_launch, "queue": queue_launch},
         "sssp": {"ms": round(float(s_ms.mean()), 4), "ms_median": round(float(np.median(s_ms)), 4),
                  "solver_kernel_ms": round(float(k_ms.mean()), 4),
                  "relaxations": int(rel), "dequeued": int(deq), "pushes": int(push),
+                 "batches": int(np.mean([x["batches"] for x in ss])),
+                 "idle_polls": int(np.mean([x["idle_polls"] for x in ss])),
                  "work_ratio_k": round(rel / m_reached, 3),
                  "relax_per_s_G": round(rel / (k_ms.mean() * 1e-3) / 1e9, 3),
                  "grid": int(ss[-1]["grid"])},

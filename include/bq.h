@@ -63,6 +63,7 @@ typedef struct {
 } bq_launch;
 
 #define BQ_F_VALIDATE 1u  /* sssp_bf: check the CSR on the device first */
+#define BQ_F_TRACE 2u     /* sssp_bf: record a timeline (see sssp_last_trace) */
 
 /* Counters of one bq_bench_mixed run. */
 typedef struct {
@@ -80,6 +81,8 @@ typedef struct {
     uint64_t batches;      /* wave dequeue batches */
     uint64_t walks;        /* parent-pointer walks (negative-cycle search) */
     uint64_t improvements; /* successful atomicMin lowering a distance */
+    uint64_t idle_polls;   /* dequeue attempts that found the queue empty */
+    uint64_t ticket_spins; /* extra polls of slot words in ticket waits */
     double ms;             /* device time of the call (HIP events) */
     double solve_ms;       /* the persistent solver kernel alone (HIP events) */
     int32_t grid;          /* workgroups launched */
@@ -136,14 +139,18 @@ bq_status bq_counters(bq_queue* q, void* stream, uint64_t* h_head, uint64_t* h_t
                       int64_t* h_count);
 
 /* Section IV "Global Mixed": a co-resident grid in which even workgroups
- * perform n_ops/2 enqueues and odd workgroups n_ops/2 dequeues, each lane
- * retrying an operation that returned Full/Empty until it succeeds. The
- * value enqueued by operation i is i. If d_enq_log / d_deq_log are not NULL
- * (device, int32[n_ops/2] each) the value written at / read from queue
- * position P - P0 is stored at index P - P0 (P0 = tail before the call), for
- * checking the position rule, conservation and per-producer order. The
- * producer of value i is lane (i mod 64) of enqueuer wave ((i / 64) mod W),
- * W = *h_enq_waves on return. Synchronous. */
+ * perform n_ops/2 enqueues and odd workgroups n_ops/2 dequeues. A wave takes
+ * chunks of K = 64*b operations (b = launch->ticket_batch, 64*b <= capacity)
+ * and moves each chunk with one broker reservation and one head/tail ticket
+ * when the queue state allows; attempts that find the queue Full / Empty are
+ * counted and retried until every operation succeeded. The queue is reset to
+ * empty first. The value enqueued by operation i is i. If d_enq_log /
+ * d_deq_log are not NULL (device, int32[n_ops/2] each) the value written at /
+ * read from queue position P is stored at index P, for checking the
+ * position rule, conservation and per-producer order: value i belongs to
+ * chunk c = i / K of enqueuer wave c mod W (W = *h_enq_waves on return),
+ * lane (i mod K) mod 64 of that wave, and is that lane's item number
+ * (c / W) * b + (i mod K) / 64. Synchronous. */
 bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
                          int32_t* d_enq_log, int32_t* d_deq_log, bq_bench_stats* h_out,
                          int32_t* h_enq_waves, void* stream);
@@ -177,8 +184,26 @@ bq_status sssp_bf(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
                   int32_t* d_pred, int32_t* h_neg_cycle, const bq_launch* launch,
                   void* stream);
 
+/* Autotuner: time sssp_bf on this input (d_dist is used as scratch) for
+ * workgroup counts 4, 8, 16, ... up to the co-resident maximum (stopping
+ * once clearly past the fastest) and then ticket batches b = 2, 4 around
+ * the fastest count; `reps` runs per candidate (the fastest counts).
+ * *h_best gets the fastest launch (other fields copied from `base`, which
+ * may be NULL), *h_best_ms its time. Synchronous. */
+bq_status sssp_autotune(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
+                        const int32_t* d_cols, const int32_t* d_w, int32_t src, int64_t* d_dist,
+                        const bq_launch* base, int32_t reps, bq_launch* h_best,
+                        double* h_best_ms, void* stream);
+
 /* Work counters and device time of the last call on ctx. */
 bq_status sssp_last_stats(const sssp_ctx* ctx, sssp_stats* h_out);
+
+/* Timeline of the last sssp_bf call made with BQ_F_TRACE: up to cap_samples
+ * samples of 4 uint64 each, (time since start in 10 ns ticks, items dequeued
+ * so far, queue length, pending work); one sample each time the dequeued
+ * work crosses a multiple of 2^k items (k chosen from n and m), unused
+ * samples all ones. Returns the number of samples written, or BQ_EINVAL. */
+int32_t sssp_last_trace(const sssp_ctx* ctx, uint64_t* h_out, int32_t cap_samples);
 
 /* ------------------------------------------------------------------------
  * Roofline probes (measurement only)

@@ -19,11 +19,13 @@ LIB_PATH = os.path.join(HERE, "libbqsssp.so")
 
 BQ_OK, BQ_EINVAL, BQ_ENOMEM, BQ_EHIP, BQ_ERANGE, BQ_ETIMEOUT, BQ_EBUSY = 0, -1, -2, -3, -4, -5, -6
 BQ_F_VALIDATE = 1
+BQ_F_TRACE = 2
 
 # every symbol include/bq.h declares
 EXPORTS = [
     "bq_create", "bq_destroy", "bq_reset", "bq_enqueue", "bq_dequeue", "bq_counters",
     "bq_bench_mixed", "sssp_ctx_create", "sssp_ctx_destroy", "sssp_bf", "sssp_last_stats",
+    "sssp_last_trace", "sssp_autotune",
     "bq_strerror", "bq_device_cus", "bq_probe",
 ]
 
@@ -50,7 +52,8 @@ class SsspStats(ctypes.Structure):
     _fields_ = [("dequeued", ctypes.c_uint64), ("relaxations", ctypes.c_uint64),
                 ("pushes", ctypes.c_uint64), ("fanout", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("walks", ctypes.c_uint64),
-                ("improvements", ctypes.c_uint64), ("ms", ctypes.c_double),
+                ("improvements", ctypes.c_uint64), ("idle_polls", ctypes.c_uint64),
+                ("ticket_spins", ctypes.c_uint64), ("ms", ctypes.c_double),
                 ("solve_ms", ctypes.c_double), ("grid", ctypes.c_int32),
                 ("wg_size", ctypes.c_int32)]
 
@@ -86,6 +89,9 @@ def lib(path: str | None = None):
         "sssp_ctx_destroy": ([vp], i32),
         "sssp_bf": ([vp, i32, i64, vp, vp, vp, i32, vp, vp, P(i32), P(Launch), vp], i32),
         "sssp_last_stats": ([vp, P(SsspStats)], i32),
+        "sssp_last_trace": ([vp, P(u64), i32], i32),
+        "sssp_autotune": ([vp, i32, i64, vp, vp, vp, i32, vp, P(Launch), i32, P(Launch),
+                           P(ctypes.c_double), vp], i32),
         "bq_strerror": ([i32], ctypes.c_char_p),
         "bq_device_cus": ([], i32),
         "bq_probe": ([i32, vp, vp, u64, u64, i32, i32, P(ctypes.c_double), vp], i32),
@@ -224,7 +230,7 @@ class SsspContext:
     __del__ = close
 
     def solve(self, offsets, cols, w, src: int, dist=None, pred=None, want_pred=True,
-              launch=None, validate=False, stream=None):
+              launch=None, validate=False, trace=False, stream=None):
         """sssp_bf on device tensors; returns (dist int64, pred int32 or None, neg bool)."""
         import torch
         n = offsets.numel() - 1
@@ -241,14 +247,36 @@ class SsspContext:
         if pred is not None:
             _need(pred, torch.int32, "pred", n)
         L = launch
-        if validate:
+        if validate or trace:
             L = Launch(**(launch or {})) if not isinstance(launch, Launch) else launch
-            L.flags |= BQ_F_VALIDATE
+            L.flags |= (BQ_F_VALIDATE if validate else 0) | (BQ_F_TRACE if trace else 0)
         neg = ctypes.c_int32(0)
         _check(lib().sssp_bf(self.handle, n, m, _ptr(offsets), _ptr(cols), _ptr(w), int(src),
                              _ptr(dist), _ptr(pred), ctypes.byref(neg), _launch(L),
                              _stream(stream)), "sssp_bf")
         return dist, pred, bool(neg.value)
+
+    def autotune(self, offsets, cols, w, src: int, reps: int = 2, base=None, stream=None):
+        """sssp_autotune: returns (launch dict, best ms)."""
+        import torch
+        n = offsets.numel() - 1
+        m = cols.numel()
+        scratch = torch.empty(n, dtype=torch.int64, device=offsets.device)
+        best = Launch()
+        ms = ctypes.c_double()
+        _check(lib().sssp_autotune(self.handle, n, m, _ptr(offsets), _ptr(cols), _ptr(w), int(src),
+                                   _ptr(scratch), _launch(base), int(reps), ctypes.byref(best),
+                                   ctypes.byref(ms), _stream(stream)), "sssp_autotune")
+        return {k: getattr(best, k) for k, _ in best._fields_}, ms.value
+
+    def trace(self):
+        """Timeline of the last solve run with flag BQ_F_TRACE: rows of
+        (ticks since start, dequeued so far, queue length, pending)."""
+        import numpy as np
+        buf = (ctypes.c_uint64 * (4 * 4096))()
+        k = lib().sssp_last_trace(self.handle, buf, 4096)
+        a = np.frombuffer(buf, dtype=np.uint64).reshape(-1, 4)[:max(k, 0)]
+        return a[a[:, 0] != np.iinfo(np.uint64).max]
 
     def stats(self) -> dict:
         s = SsspStats()

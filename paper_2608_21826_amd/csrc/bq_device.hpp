@@ -17,11 +17,9 @@
 // rank among them (mbcnt). So a wave costs two contended atomics per batch
 // instead of 2 per item. The per-slot ticket handshake stays per lane.
 //
-// Memory ordering: slot and ticket accesses use agent-scope atomics; a wave
-// that saw its tickets runs one agent-scope acquire fence before touching
-// the slots, and one agent-scope release fence before publishing tickets.
-// On a multi-XCD gfx950 agent these fences are what makes data written by a
-// wave on one XCD visible to a wave on another (separate L2s).
+// Memory ordering: every queue word is accessed with agent-scope atomics
+// (coherent across the separate L2s of the XCDs); ticket and payload share
+// one word (see Queue), so the protocol needs no fences.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -40,9 +38,10 @@ enum : int {
     ERR_NONE = 0,
     ERR_TIMEOUT = 1,   // watchdog fired inside a wait
     ERR_RANGE = 2,     // key packing precondition failed
+    ERR_FULL = 3,      // solver queue overflow (cannot happen by construction)
 };
 
-enum : int { ST_DEQ = 0, ST_RELAX, ST_PUSH, ST_FANOUT, ST_BATCH, ST_WALK, ST_SPIN, ST_IMPROVE, ST_N };
+enum : int { ST_DEQ = 0, ST_RELAX, ST_PUSH, ST_FANOUT, ST_BATCH, ST_WALK, ST_SPIN, ST_IMPROVE, ST_IDLE, ST_POLL, ST_N };
 
 struct Ctrl {
     Word head;       // next dequeue position (monotone)
@@ -115,15 +114,20 @@ __device__ __forceinline__ void backoff(int level) {
     }
 }
 
-// Longer sleeps for waves that found no work: up to ~16 us between polls so
-// thousands of idle waves do not flood the count/pending lines.
-__device__ __forceinline__ void idle_backoff(int level) {
-    if (level < 4) {
-        backoff(level);
-        return;
+// Sleep of a wave that watches for work: doubles with `level` from one
+// s_sleep unit (64 clocks) up to `max_units`. Callers size max_units to the
+// number of watchers so that together they poll the hot lines at a bounded
+// rate.
+__device__ __forceinline__ void idle_backoff(int level, unsigned max_units) {
+    unsigned units = level >= 20 ? max_units : (1u << level);
+    if (units > max_units) units = max_units;
+    while (units >= 127u) {
+        __builtin_amdgcn_s_sleep(127);
+        units -= 127u;
     }
-    const int reps = 1 << (level - 4);  // 1..8 x 127 units of 64 clocks
-    for (int i = 0; i < reps; ++i) __builtin_amdgcn_s_sleep(127);
+    if (units >= 32u) __builtin_amdgcn_s_sleep(32);
+    else if (units >= 8u) __builtin_amdgcn_s_sleep(8);
+    else __builtin_amdgcn_s_sleep(1);
 }
 
 // 100 MHz constant clock (s_memrealtime)
@@ -131,15 +135,26 @@ __device__ __forceinline__ unsigned long long now_ticks() { return wall_clock64(
 
 // ---------------------------------------------------------------------------
 // queue view
+//
+// Slot layout (gfx950 form of Alg. 1's RingBuffer and Tickets): slot i is one
+// 64-bit word, ticket in the high half and payload in the low half. The
+// ticket handshake of PUT_DATA / READ_DATA then happens on a single word:
+// the enqueuer that sees ticket 2r stores (2r+1, value) in one atomic store,
+// the dequeuer that sees (2r+1, value) has the value in the same load and
+// stores (2r+2, 0). Coherence of that one word orders everything, so no
+// cross-XCD fence (L2 writeback / invalidate) is needed per operation.
 // ---------------------------------------------------------------------------
 struct Queue {
-    uint32_t* tickets;   // [N]
-    uint32_t* ring;      // [N]
+    unsigned long long* slots;  // [N] (ticket << 32 | payload)
     Ctrl* ctrl;
     uint32_t logN;
     uint32_t pad;
     unsigned long long N;
 };
+
+__device__ __forceinline__ unsigned long long slot_word(uint32_t ticket, uint32_t val) {
+    return ((unsigned long long)ticket << 32) | val;
+}
 
 // wave-uniform read of the abort word
 __device__ __forceinline__ bool aborted(const Queue& q) {
@@ -178,12 +193,20 @@ __device__ __forceinline__ uint32_t reserve_enqueue(const Queue& q, uint32_t k) 
     return e;
 }
 
-// ENSURE for k dequeues (leader lane only), mirror image (reading of the
-// dequeue broker: success when the count before the decrement was > 0).
-__device__ __forceinline__ uint32_t reserve_dequeue(const Queue& q, uint32_t k) {
+// ENSURE for up to k dequeues (leader lane only), mirror image (reading of
+// the dequeue broker: success when the count before the decrement was > 0).
+// Asks only for what the count showed, so a crowd of idle waves does not
+// drive the count far below zero.
+// With `optimistic` (the caller's last reservation was full) the look at the
+// count is skipped and k is asked for directly.
+__device__ __forceinline__ uint32_t reserve_dequeue(const Queue& q, uint32_t k,
+                                                    bool optimistic = false) {
     long long* cnt = reinterpret_cast<long long*>(&q.ctrl->count.v);
-    long long num = ld_rlx(cnt);
-    if (num <= 0) return 0;
+    if (!optimistic) {
+        long long num = ld_rlx(cnt);
+        if (num <= 0) return 0;
+        if (num < (long long)k) k = (uint32_t)num;
+    }
     long long old = add_rlx(cnt, -(long long)k);
     uint32_t e = old <= 0 ? 0u : (old >= (long long)k ? k : (uint32_t)old);
     if (e < k) add_rlx(cnt, (long long)(k - e));
@@ -201,16 +224,22 @@ __device__ __forceinline__ bool looks_empty(const Queue& q) {
     return (long long)(t - h) <= 0;
 }
 
-// Wait until every active lane's slot carries its expected ticket. Whole
-// wave loops together. Returns false on abort/timeout.
-__device__ __forceinline__ bool wait_tickets(const Queue& q, bool active, uint32_t slot,
-                                             uint32_t want, unsigned long long limit,
-                                             unsigned long long& spins) {
+// WAIT_FOR_TICKET for every active lane: poll the lane's slot word until its
+// ticket half equals `want`; the word last read is returned in `word`. The
+// whole wave loops together. Returns false on abort / watchdog.
+__device__ __forceinline__ bool wait_slot(const Queue& q, bool active, unsigned long long pos,
+                                          uint32_t want, unsigned long long& word,
+                                          unsigned long long limit, unsigned long long& spins) {
+    const unsigned long long* p = &q.slots[pos & (q.N - 1ull)];
     Watch wd;
     wd.arm(limit);
     int level = 0;
     for (uint32_t it = 0;; ++it) {
-        bool ready = !active || ld_rlx(&q.tickets[slot]) == want;
+        bool ready = true;
+        if (active) {
+            word = ld_rlx(p);
+            ready = (uint32_t)(word >> 32) == want;
+        }
         if (__all(ready)) return true;
         ++spins;
         if ((it & 63u) == 63u) {
@@ -225,33 +254,34 @@ __device__ __forceinline__ bool wait_tickets(const Queue& q, bool active, uint32
     }
 }
 
-// PUT_DATA for lanes with `active`: positions base + rank. Values are written
-// after the acquire fence that follows the ticket wait and published by
-// release fence + ticket store.
+__device__ __forceinline__ uint32_t round_of(const Queue& q, unsigned long long pos) {
+    return (uint32_t)(pos >> q.logN);
+}
+
+// PUT_DATA for active lanes at their positions: wait for ticket 2r, store
+// (2r+1, value).
 __device__ __forceinline__ bool put_slots(const Queue& q, bool active, unsigned long long pos,
                                           uint32_t val, unsigned long long limit,
                                           unsigned long long& spins) {
-    const uint32_t slot = (uint32_t)(pos & (q.N - 1));
-    const uint32_t round = (uint32_t)(pos >> q.logN);
-    if (!wait_tickets(q, active, slot, 2u * round, limit, spins)) return false;
-    fence_acquire();
-    if (active) st_rlx(&q.ring[slot], val);
-    fence_release();
-    if (active) st_rlx(&q.tickets[slot], 2u * round + 1u);
+    const uint32_t r = round_of(q, pos);
+    unsigned long long w = 0;
+    if (!wait_slot(q, active, pos, 2u * r, w, limit, spins)) return false;
+    if (active) st_rlx(&q.slots[pos & (q.N - 1ull)], slot_word(2u * r + 1u, val));
     return true;
 }
 
-// READ_DATA: wait for 2r+1, read, hand the slot to round r+1 with 2(r+1).
+// READ_DATA: wait for (2r+1, value), take the value, hand the slot to round
+// r+1 by storing (2(r+1), 0).
 __device__ __forceinline__ bool read_slots(const Queue& q, bool active, unsigned long long pos,
                                            uint32_t& val, unsigned long long limit,
                                            unsigned long long& spins) {
-    const uint32_t slot = (uint32_t)(pos & (q.N - 1));
-    const uint32_t round = (uint32_t)(pos >> q.logN);
-    if (!wait_tickets(q, active, slot, 2u * round + 1u, limit, spins)) return false;
-    fence_acquire();
-    if (active) val = ld_rlx(&q.ring[slot]);
-    fence_release();
-    if (active) st_rlx(&q.tickets[slot], 2u * (round + 1u));
+    const uint32_t r = round_of(q, pos);
+    unsigned long long w = 0;
+    if (!wait_slot(q, active, pos, 2u * r + 1u, w, limit, spins)) return false;
+    if (active) {
+        val = (uint32_t)w;
+        st_rlx(&q.slots[pos & (q.N - 1ull)], slot_word(2u * (r + 1u), 0u));
+    }
     return true;
 }
 

@@ -18,8 +18,7 @@ struct bq_queue {
     int device;
     uint32_t capacity;
     uint32_t logN;
-    uint32_t* tickets;
-    uint32_t* ring;
+    unsigned long long* slots;   // [capacity] (ticket << 32 | payload)
     bq::Ctrl* ctrl;
     unsigned long long* scratch;  // device counters for the bench
     hipEvent_t ev0, ev1;
@@ -27,10 +26,9 @@ struct bq_queue {
 
 namespace {
 
-__device__ __forceinline__ Queue view(uint32_t* t, uint32_t* r, bq::Ctrl* c, uint32_t logN) {
+__device__ __forceinline__ Queue view(unsigned long long* sl, bq::Ctrl* c, uint32_t logN) {
     Queue q;
-    q.tickets = t;
-    q.ring = r;
+    q.slots = sl;
     q.ctrl = c;
     q.logN = logN;
     q.pad = 0;
@@ -148,10 +146,10 @@ __device__ int wave_dequeue_one(const Queue& q, bool active, uint32_t& val, bool
     return result;
 }
 
-__global__ void k_bulk_enqueue(uint32_t* tickets, uint32_t* ring, bq::Ctrl* ctrl, uint32_t logN,
+__global__ void k_bulk_enqueue(unsigned long long* slots, bq::Ctrl* ctrl, uint32_t logN,
                                const int32_t* vals, unsigned long long n,
                                unsigned long long* n_ok, unsigned long long limit) {
-    const Queue q = view(tickets, ring, ctrl, logN);
+    const Queue q = view(slots, ctrl, logN);
     const unsigned long long waves = (unsigned long long)gridDim.x * (blockDim.x >> 6);
     const unsigned long long wave = (unsigned long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     unsigned long long ok = 0, spins = 0, fails = 0;
@@ -168,10 +166,10 @@ __global__ void k_bulk_enqueue(uint32_t* tickets, uint32_t* ring, bq::Ctrl* ctrl
     if (bq::lane_id() == 0 && ok) bq::add_rlx(n_ok, ok);
 }
 
-__global__ void k_bulk_dequeue(uint32_t* tickets, uint32_t* ring, bq::Ctrl* ctrl, uint32_t logN,
+__global__ void k_bulk_dequeue(unsigned long long* slots, bq::Ctrl* ctrl, uint32_t logN,
                                int32_t* out, unsigned long long n, unsigned long long* n_ok,
                                unsigned long long limit) {
-    const Queue q = view(tickets, ring, ctrl, logN);
+    const Queue q = view(slots, ctrl, logN);
     const unsigned long long waves = (unsigned long long)gridDim.x * (blockDim.x >> 6);
     const unsigned long long wave = (unsigned long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     unsigned long long spins = 0, fails = 0;
@@ -191,41 +189,85 @@ __global__ void k_bulk_dequeue(uint32_t* tickets, uint32_t* ring, bq::Ctrl* ctrl
     }
 }
 
-// Section IV "Global Mixed": even workgroups enqueue, odd dequeue. Each op
-// retries Full/Empty until it succeeds. stats[0..3] = enq_ok, deq_ok,
+// Section IV "Global Mixed": even workgroups enqueue, odd dequeue. A wave
+// takes chunks of K = 64*b operations (grid-stride over chunks); each chunk
+// is moved with as few broker reservations and head/tail tickets as the
+// queue state allows (one of each when it fits), and an attempt that finds
+// the queue Full / Empty is retried after a backoff until the chunk is done.
+// Enqueue operation i writes value i. stats[0..3] = enq_ok, deq_ok,
 // enq_full, deq_empty.
-__global__ void k_bench_mixed(uint32_t* tickets, uint32_t* ring, bq::Ctrl* ctrl, uint32_t logN,
+__global__ void k_bench_mixed(unsigned long long* slots, bq::Ctrl* ctrl, uint32_t logN,
                               unsigned long long n_half, int32_t* enq_log, int32_t* deq_log,
                               unsigned long long pos0, unsigned long long* stats,
-                              unsigned long long limit) {
-    const Queue q = view(tickets, ring, ctrl, logN);
+                              unsigned long long limit, unsigned b) {
+    const Queue q = view(slots, ctrl, logN);
+    const int lane = bq::lane_id();
     const int wpb = blockDim.x >> 6;
     const bool enq = (blockIdx.x & 1u) == 0u;
     const unsigned long long role_blocks = enq ? (gridDim.x + 1u) / 2u : gridDim.x / 2u;
     const unsigned long long waves = role_blocks * (unsigned long long)wpb;
     const unsigned long long wave = (unsigned long long)(blockIdx.x >> 1) * wpb + (threadIdx.x >> 6);
+    const unsigned long long K = 64ull * b;
     unsigned long long ok = 0, spins = 0, fails = 0;
-    for (unsigned long long c = wave; c * 64ull < n_half; c += waves) {
-        const unsigned long long i = c * 64ull + (unsigned long long)bq::lane_id();
-        const bool active = i < n_half;
-        unsigned long long pos = 0;
-        int r;
-        if (enq) {
-            r = wave_enqueue_one(q, active, (uint32_t)i, false, limit, spins, fails, &pos);
-            if (r == 1 && enq_log) enq_log[pos - pos0] = (int32_t)i;
-        } else {
-            uint32_t v = 0;
-            r = wave_dequeue_one(q, active, v, false, limit, spins, fails, &pos);
-            if (r == 1 && deq_log) deq_log[pos - pos0] = (int32_t)v;
+    bool bad = false;
+    for (unsigned long long c = wave; c * K < n_half && !bad; c += waves) {
+        const unsigned long long first = c * K;
+        const unsigned long long cnt = (n_half - first) < K ? (n_half - first) : K;
+        unsigned long long done = 0;
+        int level = 0;
+        bq::Watch wd;
+        wd.arm(limit);
+        while (done < cnt) {
+            uint32_t e = 0;
+            unsigned long long base = 0;
+            if (lane == 0) {
+                const uint32_t want = (uint32_t)(cnt - done);
+                e = enq ? bq::reserve_enqueue(q, want) : bq::reserve_dequeue(q, want);
+                if (e) base = bq::add_rlx(enq ? &q.ctrl->tail.v : &q.ctrl->head.v,
+                                          (unsigned long long)e);
+            }
+            e = bq::bcast32(e);
+            base = bq::bcast64(base);
+            for (uint32_t j0 = 0; j0 < e; j0 += 64) {
+                const uint32_t j = j0 + (uint32_t)lane;
+                const bool act = j < e;
+                const unsigned long long pos = base + j;
+                if (enq) {
+                    const uint32_t val = (uint32_t)(first + done + j);
+                    if (!bq::put_slots(q, act, pos, val, limit, spins)) {
+                        bad = true;
+                        break;
+                    }
+                    if (act && enq_log) enq_log[pos - pos0] = (int32_t)val;
+                } else {
+                    uint32_t val = 0;
+                    if (!bq::read_slots(q, act, pos, val, limit, spins)) {
+                        bad = true;
+                        break;
+                    }
+                    if (act && deq_log) deq_log[pos - pos0] = (int32_t)val;
+                }
+            }
+            if (bad) break;
+            done += e;
+            ok += e;
+            if (done < cnt) {
+                ++fails;
+                if (bq::aborted(q)) {
+                    bad = true;
+                    break;
+                }
+                if (wd.expired()) {
+                    if (lane == 0) bq::raise_error(q, bq::ERR_TIMEOUT);
+                    bad = true;
+                    break;
+                }
+                bq::backoff(level);
+                if (level < 3) ++level;
+            }
         }
-        if (__any(r < 0)) break;
-        ok += (r == 1);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        ok += __shfl_xor(ok, off, 64);
-        fails += __shfl_xor(fails, off, 64);
-    }
-    if (bq::lane_id() == 0) {
+    if (lane == 0) {
         if (ok) bq::add_rlx(&stats[enq ? 0 : 1], ok);
         if (fails) bq::add_rlx(&stats[enq ? 2 : 3], fails);
     }
@@ -283,8 +325,7 @@ const char* bq_strerror(bq_status s) {
 int32_t bq_device_cus(void) { return bqh::device_cus(); }
 
 static bq_status queue_zero(bq_queue* q, hipStream_t s) {
-    BQ_HIP_TRY(hipMemsetAsync(q->tickets, 0, sizeof(uint32_t) * q->capacity, s));
-    BQ_HIP_TRY(hipMemsetAsync(q->ring, 0, sizeof(uint32_t) * q->capacity, s));
+    BQ_HIP_TRY(hipMemsetAsync(q->slots, 0, sizeof(unsigned long long) * q->capacity, s));
     BQ_HIP_TRY(hipMemsetAsync(q->ctrl, 0, sizeof(bq::Ctrl), s));
     return BQ_OK;
 }
@@ -298,8 +339,7 @@ bq_status bq_create(uint32_t capacity, uint32_t flags, void* stream, bq_queue** 
     BQ_HIP_TRY(hipGetDevice(&q->device));
     q->capacity = capacity;
     q->logN = bqh::log2_exact(capacity);
-    if (hipMalloc(&q->tickets, sizeof(uint32_t) * capacity) != hipSuccess ||
-        hipMalloc(&q->ring, sizeof(uint32_t) * capacity) != hipSuccess ||
+    if (hipMalloc(&q->slots, sizeof(unsigned long long) * capacity) != hipSuccess ||
         hipMalloc(&q->ctrl, sizeof(bq::Ctrl)) != hipSuccess ||
         hipMalloc(&q->scratch, 4096) != hipSuccess) {
         bq_destroy(q);
@@ -320,8 +360,7 @@ bq_status bq_create(uint32_t capacity, uint32_t flags, void* stream, bq_queue** 
 bq_status bq_destroy(bq_queue* q) {
     if (!q) return BQ_OK;
     (void)hipDeviceSynchronize();
-    if (q->tickets) (void)hipFree(q->tickets);
-    if (q->ring) (void)hipFree(q->ring);
+    if (q->slots) (void)hipFree(q->slots);
     if (q->ctrl) (void)hipFree(q->ctrl);
     if (q->scratch) (void)hipFree(q->scratch);
     if (q->ev0) (void)hipEventDestroy(q->ev0);
@@ -382,7 +421,7 @@ bq_status bq_enqueue(bq_queue* q, const int32_t* d_vals, uint64_t n, uint64_t* d
     BQ_HIP_TRY(hipMemsetAsync(d_n_ok, 0, 8, s));
     if (n) {
         hipLaunchKernelGGL(k_bulk_enqueue, dim3(bulk_grid(L, n)), dim3(L.wg_size), 0, s,
-                           q->tickets, q->ring, q->ctrl, q->logN, d_vals, (unsigned long long)n,
+                           q->slots, q->ctrl, q->logN, d_vals, (unsigned long long)n,
                            (unsigned long long*)d_n_ok, L.limit);
         BQ_HIP_TRY(hipGetLastError());
     }
@@ -398,7 +437,7 @@ bq_status bq_dequeue(bq_queue* q, int32_t* d_out, uint64_t n, uint64_t* d_n_ok,
     BQ_HIP_TRY(hipMemsetAsync(d_n_ok, 0, 8, s));
     if (n) {
         hipLaunchKernelGGL(k_bulk_dequeue, dim3(bulk_grid(L, n)), dim3(L.wg_size), 0, s,
-                           q->tickets, q->ring, q->ctrl, q->logN, d_out, (unsigned long long)n,
+                           q->slots, q->ctrl, q->logN, d_out, (unsigned long long)n,
                            (unsigned long long*)d_n_ok, L.limit);
         BQ_HIP_TRY(hipGetLastError());
     }
@@ -412,6 +451,7 @@ bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
     hipStream_t s = bqh::as_stream(stream);
     bqh::Launch L = bqh::resolve(launch, 0);
     if (L.wg_size % 64 || L.wg_size > 1024) return BQ_EINVAL;
+    if (L.batch < 1 || 64ull * (unsigned long long)L.batch > q->capacity) return BQ_EINVAL;
     // co-resident grid: enqueuers spin on Full until dequeuers run, so all
     // workgroups must be resident together (cooperative launch checks it)
     int per_cu = 0;
@@ -430,12 +470,12 @@ bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
     int32_t* el = d_enq_log;
     int32_t* dl = d_deq_log;
     unsigned long long* stats = q->scratch;
-    uint32_t* tk = q->tickets;
-    uint32_t* rg = q->ring;
+    unsigned long long* sl = q->slots;
     bq::Ctrl* ct = q->ctrl;
     uint32_t lg = q->logN;
     unsigned long long lim = L.limit;
-    void* args[] = {&tk, &rg, &ct, &lg, &n_half, &el, &dl, &pos0, &stats, &lim};
+    unsigned bb = (unsigned)L.batch;
+    void* args[] = {&sl, &ct, &lg, &n_half, &el, &dl, &pos0, &stats, &lim, &bb};
     BQ_HIP_TRY(hipEventRecord(q->ev0, s));
     BQ_HIP_TRY(hipLaunchCooperativeKernel((const void*)k_bench_mixed, dim3(grid), dim3(L.wg_size),
                                           args, 0, s));

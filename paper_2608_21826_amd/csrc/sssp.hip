@@ -70,6 +70,9 @@ struct SolveArgs {
     unsigned chunk_log;
     unsigned long long limit;     // one wait (ticks of the 100 MHz clock)
     unsigned long long deadline;  // whole solve
+    unsigned long long* trace;    // optional timeline: 4 words per sample
+    unsigned trace_shift;         // one sample per 2^trace_shift dequeued items
+    unsigned trace_cap;           // samples
 };
 
 __device__ __forceinline__ long long pack_key(long long d, unsigned parent, unsigned shift) {
@@ -96,8 +99,7 @@ __global__ void k_init_ctrl(Queue q, int src) {
     const unsigned long long pos = c->tail.v;
     const unsigned slot = (unsigned)(pos & (q.N - 1ull));
     const unsigned round = (unsigned)(pos >> q.logN);
-    q.ring[slot] = (unsigned)src;
-    q.tickets[slot] = 2u * round + 1u;
+    q.slots[slot] = bq::slot_word(2u * round + 1u, (unsigned)src);
     c->tail.v = pos + 1ull;
     c->count.v = 1ull;
 }
@@ -155,10 +157,11 @@ struct WaveLds {
 
 // Publish `cnt` items from the wave's LDS buffer (Alg. 1 ENQUEUE for all of
 // them at once). pending is raised by `cnt + pending_delta` before any item
-// becomes visible. Returns false on abort.
+// becomes visible. `release` orders earlier plain stores (the chunk table)
+// before the items. Returns false on abort.
 template <class LDS>
 __device__ bool flush_out(const SolveArgs& a, LDS& L, int cnt, long long pending_delta,
-                          unsigned long long& spins) {
+                          bool release, unsigned long long& spins) {
     const Queue& q = a.q;
     const int lane = bq::lane_id();
     if (cnt == 0) {
@@ -168,53 +171,25 @@ __device__ bool flush_out(const SolveArgs& a, LDS& L, int cnt, long long pending
     }
     unsigned long long base = 0;
     if (lane == 0) {
+        // pending, ENSURE on count and the tail positions as three atomics in
+        // flight together. In the solver the broker reservation cannot fail:
+        // a vertex holds at most one queue item (its q bit) and chunk items
+        // are bounded, and the capacity is twice that, so count + cnt <= N
+        // always; an overflow would be a bug and stops the solve.
         bq::add_rlx(&q.ctrl->pending.v, (unsigned long long)((long long)cnt + pending_delta));
-        // ENSURE: in the solver the queue never fills (capacity >= 2x the
-        // items that can be queued), but keep Alg. 1's retry
-        unsigned got = 0;
-        int level = 0;
-        bq::Watch wd;
-        wd.arm(a.limit);
-        while (got < (unsigned)cnt) {
-            got += bq::reserve_enqueue(q, (unsigned)cnt - got);
-            if (got < (unsigned)cnt) {
-                if (wd.expired() || bq::ld_rlx(&q.ctrl->abort.v)) {
-                    bq::raise_error(q, bq::ERR_TIMEOUT);
-                    break;
-                }
-                bq::backoff(level);
-                if (level < 3) ++level;
-            }
-        }
+        const long long old = bq::add_rlx(reinterpret_cast<long long*>(&q.ctrl->count.v),
+                                          (long long)cnt);
         base = bq::add_rlx(&q.ctrl->tail.v, (unsigned long long)cnt);
+        if (old + cnt > (long long)q.N) bq::raise_error(q, bq::ERR_FULL);
     }
     base = bq::bcast64(base);
     if (bq::aborted(q)) return false;
-    // WAIT_FOR_TICKET for every slot first, then one acquire fence, the
-    // writes, one release fence and the tickets
+    if (release) bq::fence_release();
     for (int c0 = 0; c0 < cnt; c0 += 64) {
         const int i = c0 + lane;
-        const unsigned long long pos = base + (unsigned long long)i;
-        if (!bq::wait_tickets(q, i < cnt, (unsigned)(pos & (q.N - 1ull)),
-                              2u * (unsigned)(pos >> q.logN), a.limit, spins))
+        if (!bq::put_slots(q, i < cnt, base + (unsigned long long)i, i < cnt ? L.out[i] : 0u,
+                           a.limit, spins))
             return false;
-    }
-    bq::fence_acquire();
-    for (int c0 = 0; c0 < cnt; c0 += 64) {
-        const int i = c0 + lane;
-        if (i < cnt) {
-            const unsigned long long pos = base + (unsigned long long)i;
-            bq::st_rlx(&q.ring[(unsigned)(pos & (q.N - 1ull))], L.out[i]);
-        }
-    }
-    bq::fence_release();
-    for (int c0 = 0; c0 < cnt; c0 += 64) {
-        const int i = c0 + lane;
-        if (i < cnt) {
-            const unsigned long long pos = base + (unsigned long long)i;
-            bq::st_rlx(&q.tickets[(unsigned)(pos & (q.N - 1ull))],
-                       2u * (unsigned)(pos >> q.logN) + 1u);
-        }
     }
     return true;
 }
@@ -284,10 +259,115 @@ __device__ bool walk_finds_negative_cycle(const SolveArgs& a, int x0, unsigned b
     return y == hare && sum < 0;
 }
 
+// Per-workgroup parking of idle waves: one wave of the workgroup (the
+// poller) watches the global queue state with growing sleeps; the other idle
+// waves sleep on workgroup-local flags. This keeps the number of waves
+// hammering the hot count / pending lines at one per workgroup.
+struct WgShared {
+    int poller;     // wave index of the current poller, -1 if none
+    unsigned wake;  // bumped by the poller when the count turned positive
+    int done;       // pending reached 0: every wave of the workgroup leaves
+};
+
+__device__ __forceinline__ int wg_ld(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ unsigned wg_ld(const unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void wg_st(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Wait for work. Returns 0 when the queue may hold items, 1 when all work is
+// done (pending = 0), -1 on abort / watchdog. Wave-uniform.
+__device__ int idle_wait(const SolveArgs& a, WgShared& S, int wid, unsigned long long& seen_head,
+                         bq::Watch& idle, unsigned long long t_start,
+                         unsigned long long& polls) {
+    const Queue& q = a.q;
+    const int lane = bq::lane_id();
+    while (true) {
+        if (bq::aborted(q)) return -1;
+        if (wg_ld(&S.done)) return 1;
+        int got = 0;
+        if (lane == 0) {
+            int expect = -1;
+            got = __hip_atomic_compare_exchange_strong(&S.poller, &expect, wid, __ATOMIC_RELAXED,
+                                                       __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP)
+                      ? 1
+                      : 0;
+        }
+        if (bq::bcast32((unsigned)got)) {
+            int level = 0;
+            while (true) {
+                ++polls;
+                unsigned long long pend = 0, cnt = 0, hd = 0;
+                if (lane == 0) {
+                    pend = bq::ld_rlx(&q.ctrl->pending.v);
+                    cnt = bq::ld_rlx(&q.ctrl->count.v);
+                    hd = bq::ld_rlx(&q.ctrl->head.v);
+                }
+                pend = bq::bcast64(pend);
+                cnt = bq::bcast64(cnt);
+                hd = bq::bcast64(hd);
+                if (pend == 0ull) {
+                    if (lane == 0) {
+                        wg_st(&S.done, 1);
+                        wg_st(&S.poller, -1);
+                    }
+                    return 1;
+                }
+                if ((long long)cnt > 0) {
+                    if (lane == 0) {
+                        __hip_atomic_fetch_add(&S.wake, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        wg_st(&S.poller, -1);
+                    }
+                    return 0;
+                }
+                if (hd != seen_head) {
+                    seen_head = hd;
+                    idle.arm(a.limit);
+                }
+                const bool late = idle.expired() || bq::now_ticks() - t_start > a.deadline;
+                if (late || bq::aborted(q)) {
+                    if (lane == 0) {
+                        if (late) bq::raise_error(q, bq::ERR_TIMEOUT);
+                        wg_st(&S.poller, -1);
+                    }
+                    return -1;
+                }
+                // one poller per workgroup; keep the pollers together at
+                // about one poll every 0.2 us on the hot lines
+                bq::idle_backoff(level, 8u * gridDim.x);
+                if (level < 20) ++level;
+            }
+        } else {
+            const unsigned w0 = wg_ld(&S.wake);
+            for (unsigned it = 1;; ++it) {
+                __builtin_amdgcn_s_sleep(16);
+                if (wg_ld(&S.done)) return 1;
+                if (wg_ld(&S.wake) != w0) return 0;
+                if (wg_ld(&S.poller) == -1) break;
+                if ((it & 63u) == 0u && bq::aborted(q)) return -1;
+            }
+        }
+    }
+}
+
 template <int B>
 __global__ __launch_bounds__(SOLVE_WG) void k_solve(SolveArgs a) {
     __shared__ WaveLds<B> lds[WAVES_PER_WG];
+    __shared__ WgShared S;
     WaveLds<B>& L = lds[threadIdx.x >> 6];
+    const int wid = (int)(threadIdx.x >> 6);
+    if (threadIdx.x == 0) {
+        S.poller = -1;
+        S.wake = 0u;
+        S.done = 0;
+    }
+    __syncthreads();
     const Queue& q = a.q;
     const int lane = bq::lane_id();
     const unsigned shift = a.shift;
@@ -320,8 +400,8 @@ __global__ __launch_bounds__(SOLVE_WG) void k_solve(SolveArgs a) {
     const unsigned long long t_start = bq::ld_rlx(&q.ctrl->aux[4].v);
 
     unsigned long long st_deq = 0, st_relax = 0, st_push = 0, st_fan = 0, st_batch = 0,
-                       st_walk = 0, st_impr = 0, spins = 0;
-    int level = 0;
+                       st_walk = 0, st_impr = 0, spins = 0, st_idle = 0, st_poll = 0;
+    bool had_work = true;  // the first attempt goes straight to the count
     // an idle wave gives up only if the whole queue stops moving (head
     // unchanged for `limit`) while work is still pending
     bq::Watch idle;
@@ -338,58 +418,48 @@ __global__ __launch_bounds__(SOLVE_WG) void k_solve(SolveArgs a) {
         unsigned e = 0;
         unsigned long long base = 0;
         if (lane == 0) {
-            e = bq::reserve_dequeue(q, (unsigned)B);
+            e = bq::reserve_dequeue(q, (unsigned)B, had_work);
             if (e) base = bq::add_rlx(&q.ctrl->head.v, (unsigned long long)e);
         }
         e = bq::bcast32(e);
+        had_work = e > 0;
         if (e == 0) {
-            unsigned long long pend = 0, hd = 0;
-            if (lane == 0) {
-                pend = bq::ld_rlx(&q.ctrl->pending.v);
-                hd = bq::ld_rlx(&q.ctrl->head.v);
-            }
-            if (bq::bcast64(pend) == 0ull) break;
-            hd = bq::bcast64(hd);
-            if (hd != seen_head) {
-                seen_head = hd;
-                idle.arm(a.limit);
-            }
-            if (idle.expired()) {
-                if (lane == 0) bq::raise_error(q, bq::ERR_TIMEOUT);
-                break;
-            }
-            bq::idle_backoff(level);
-            if (level < 7) ++level;
+            ++st_idle;
+            if (idle_wait(a, S, wid, seen_head, idle, t_start, st_poll) != 0) break;
+            had_work = true;  // the poller saw a positive count
             continue;
         }
-        level = 0;
         idle.arm(a.limit);
         base = bq::bcast64(base);
         ++st_batch;
         st_deq += e;
         bool ok = true;
+        bool any_chunk = false;
         for (unsigned c0 = 0; c0 < e; c0 += 64) {
             const unsigned i = c0 + lane;
-            const unsigned long long pos = base + i;
-            if (!bq::wait_tickets(q, i < e, (unsigned)(pos & (q.N - 1ull)),
-                                  2u * (unsigned)(pos >> q.logN) + 1u, a.limit, spins)) {
+            unsigned v = 0;
+            if (!bq::read_slots(q, i < e, base + i, v, a.limit, spins)) {
                 ok = false;
                 break;
             }
+            if (i < e) L.item[i] = v;
+            any_chunk |= __any(i < e && v >= n);
         }
         if (!ok) break;
-        bq::fence_acquire();
-        for (unsigned c0 = 0; c0 < e; c0 += 64) {
-            const unsigned i = c0 + lane;
-            if (i < e) L.item[i] = bq::ld_rlx(&q.ring[(unsigned)((base + i) & (q.N - 1ull))]);
-        }
-        bq::fence_release();
-        for (unsigned c0 = 0; c0 < e; c0 += 64) {
-            const unsigned i = c0 + lane;
-            if (i < e) {
-                const unsigned long long pos = base + i;
-                bq::st_rlx(&q.tickets[(unsigned)(pos & (q.N - 1ull))],
-                           2u * ((unsigned)(pos >> q.logN) + 1u));
+        // chunk items name their row through chunk_owner, written before
+        // the items were published (release fence on that side)
+        if (any_chunk) bq::fence_acquire();
+        if (a.trace) {
+            const unsigned long long w0 = base - head0, w1 = w0 + e;
+            if ((w0 >> a.trace_shift) != (w1 >> a.trace_shift) && lane == 0) {
+                const unsigned long long idx = w1 >> a.trace_shift;
+                if (idx < a.trace_cap) {
+                    unsigned long long* t = a.trace + 4ull * idx;
+                    t[0] = bq::now_ticks() - t_start;
+                    t[1] = w1;
+                    t[2] = bq::ld_rlx(&q.ctrl->tail.v) - bq::ld_rlx(&q.ctrl->head.v);
+                    t[3] = bq::ld_rlx(&q.ctrl->pending.v);
+                }
             }
         }
 
@@ -459,7 +529,7 @@ __global__ __launch_bounds__(SOLVE_WG) void k_solve(SolveArgs a) {
                     }
                     const int cnt_now = (ftot - t0) < 64 ? (ftot - t0) : 64;
                     __builtin_amdgcn_wave_barrier();
-                    if (!flush_out(a, L, cnt_now, 0, spins)) {
+                    if (!flush_out(a, L, cnt_now, 0, true, spins)) {
                         ok = false;
                         break;
                     }
@@ -526,7 +596,7 @@ __global__ __launch_bounds__(SOLVE_WG) void k_solve(SolveArgs a) {
             }
             if (nout > OUTCAP - 256) {
                 __builtin_amdgcn_wave_barrier();
-                if (!flush_out(a, L, nout, 0, spins)) {
+                if (!flush_out(a, L, nout, 0, false, spins)) {
                     ok = false;
                     break;
                 }
@@ -538,7 +608,7 @@ __global__ __launch_bounds__(SOLVE_WG) void k_solve(SolveArgs a) {
         if (!ok) break;
         __builtin_amdgcn_wave_barrier();
         // publish the rest and retire this batch in one pending update
-        if (!flush_out(a, L, nout, -(long long)e, spins)) break;
+        if (!flush_out(a, L, nout, -(long long)e, false, spins)) break;
         st_push += (unsigned long long)nout;
 
         // ---- negative-cycle search once the work looks unbounded --------
@@ -566,6 +636,8 @@ __global__ __launch_bounds__(SOLVE_WG) void k_solve(SolveArgs a) {
         if (st_batch) bq::add_rlx(&c->stats[bq::ST_BATCH].v, st_batch);
         if (st_walk) bq::add_rlx(&c->stats[bq::ST_WALK].v, st_walk);
         if (spins) bq::add_rlx(&c->stats[bq::ST_SPIN].v, spins);
+        if (st_idle) bq::add_rlx(&c->stats[bq::ST_IDLE].v, st_idle);
+        if (st_poll) bq::add_rlx(&c->stats[bq::ST_POLL].v, st_poll);
     }
     // improvements are per lane
     for (int off = 32; off > 0; off >>= 1) st_impr += __shfl_xor(st_impr, off, 64);
@@ -596,10 +668,12 @@ struct sssp_ctx {
     int max_n;
     long long max_m;
     uint32_t capacity, logN;
-    uint32_t* tickets;
-    uint32_t* ring;
+    unsigned long long* slots;
     bq::Ctrl* ctrl;
     unsigned* chunk_owner;
+    unsigned long long* trace;    // [4 * TRACE_CAP]
+    unsigned long long* h_trace;  // pinned copy
+    int trace_n;
     unsigned chunk_log;
     bq::Ctrl* h_ctrl;  // pinned copy of the control block
     hipEvent_t ev0, ev1, evs0, evs1;
@@ -611,10 +685,10 @@ struct sssp_ctx {
 namespace {
 
 constexpr unsigned DEFAULT_CHUNK_LOG = 10;  // rows longer than 1024 edges are split
+constexpr int TRACE_CAP = 4096;
 
 bq_status ctx_reset_queue(sssp_ctx* c, hipStream_t s) {
-    BQ_HIP_TRY(hipMemsetAsync(c->tickets, 0, sizeof(uint32_t) * c->capacity, s));
-    BQ_HIP_TRY(hipMemsetAsync(c->ring, 0, sizeof(uint32_t) * c->capacity, s));
+    BQ_HIP_TRY(hipMemsetAsync(c->slots, 0, sizeof(unsigned long long) * c->capacity, s));
     BQ_HIP_TRY(hipMemsetAsync(c->ctrl, 0, sizeof(bq::Ctrl), s));
     c->dirty = false;
     return BQ_OK;
@@ -622,8 +696,7 @@ bq_status ctx_reset_queue(sssp_ctx* c, hipStream_t s) {
 
 Queue ctx_queue(const sssp_ctx* c) {
     Queue q;
-    q.tickets = c->tickets;
-    q.ring = c->ring;
+    q.slots = c->slots;
     q.ctrl = c->ctrl;
     q.logN = c->logN;
     q.pad = 0;
@@ -644,6 +717,18 @@ int grid_for(int n_items) {
     return g < 1 ? 1 : g;
 }
 
+// Default workgroup count when the caller gives none: about one workgroup
+// (4 waves) per 16K units of n + m/16, a power of two between 4 and the
+// co-resident maximum. More waves than the work can feed only add traffic on
+// the queue's hot lines and extra relaxations (labels scanned before they
+// settle); sssp_autotune measures instead of guessing.
+int default_grid(int n, long long m, int max_grid) {
+    const unsigned long long units = (unsigned long long)n + (unsigned long long)m / 16ull;
+    int g = 4;
+    while ((unsigned long long)g * 2ull * 16384ull <= units && g * 2 <= max_grid) g *= 2;
+    return g < max_grid ? g : max_grid;
+}
+
 template <int B>
 bq_status launch_solve(sssp_ctx* c, const SolveArgs& args, const bqh::Launch& L, hipStream_t s,
                        int slot, int* grid_out) {
@@ -653,7 +738,7 @@ bq_status launch_solve(sssp_ctx* c, const SolveArgs& args, const bqh::Launch& L,
         if (per_cu < 1) per_cu = 1;
     }
     const int max_grid = per_cu * bqh::device_cus();
-    int grid = L.wg_count > 0 ? L.wg_count : max_grid;
+    int grid = L.wg_count > 0 ? L.wg_count : default_grid(args.n, args.m, max_grid);
     if (grid > max_grid) grid = max_grid;  // all waves co-resident
     *grid_out = grid;
     hipLaunchKernelGGL(k_solve<B>, dim3(grid), dim3(SOLVE_WG), 0, s, args);
@@ -687,8 +772,10 @@ bq_status sssp_ctx_create(int32_t max_n, int64_t max_m, sssp_ctx** out) {
     c->capacity = (uint32_t)cap;
     c->logN = bqh::log2_exact(cap);
     const size_t chunks = (size_t)((unsigned long long)max_m >> c->chunk_log) + 1;
-    if (hipMalloc(&c->tickets, sizeof(uint32_t) * cap) != hipSuccess ||
-        hipMalloc(&c->ring, sizeof(uint32_t) * cap) != hipSuccess ||
+    if (hipMalloc(&c->slots, sizeof(unsigned long long) * cap) != hipSuccess ||
+        hipMalloc(&c->trace, sizeof(unsigned long long) * 4 * TRACE_CAP) != hipSuccess ||
+        hipHostMalloc(&c->h_trace, sizeof(unsigned long long) * 4 * TRACE_CAP,
+                      hipHostMallocDefault) != hipSuccess ||
         hipMalloc(&c->ctrl, sizeof(bq::Ctrl)) != hipSuccess ||
         hipMalloc(&c->chunk_owner, sizeof(unsigned) * chunks) != hipSuccess ||
         hipHostMalloc(&c->h_ctrl, sizeof(bq::Ctrl), hipHostMallocDefault) != hipSuccess) {
@@ -712,8 +799,9 @@ bq_status sssp_ctx_create(int32_t max_n, int64_t max_m, sssp_ctx** out) {
 bq_status sssp_ctx_destroy(sssp_ctx* c) {
     if (!c) return BQ_OK;
     (void)hipDeviceSynchronize();
-    if (c->tickets) (void)hipFree(c->tickets);
-    if (c->ring) (void)hipFree(c->ring);
+    if (c->slots) (void)hipFree(c->slots);
+    if (c->trace) (void)hipFree(c->trace);
+    if (c->h_trace) (void)hipHostFree(c->h_trace);
     if (c->ctrl) (void)hipFree(c->ctrl);
     if (c->chunk_owner) (void)hipFree(c->chunk_owner);
     if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
@@ -723,6 +811,78 @@ bq_status sssp_ctx_destroy(sssp_ctx* c) {
     if (c->evs1) (void)hipEventDestroy(c->evs1);
     free(c);
     return BQ_OK;
+}
+
+bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
+                        const int32_t* d_cols, const int32_t* d_w, int32_t src, int64_t* d_dist,
+                        const bq_launch* base, int32_t reps, bq_launch* h_best,
+                        double* h_best_ms, void* stream) {
+    if (!c || !h_best || !h_best_ms || !d_dist) return BQ_EINVAL;
+    if (reps < 1) reps = 2;
+    bq_launch L = {};
+    if (base) L = *base;
+    L.flags &= ~(uint32_t)(BQ_F_TRACE | BQ_F_VALIDATE);
+    int per_cu = c->solve_per_cu[0];
+    if (per_cu == 0) {
+        BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<64>, SOLVE_WG, 0));
+        if (per_cu < 1) per_cu = 1;
+        c->solve_per_cu[0] = per_cu;
+    }
+    const int max_grid = per_cu * bqh::device_cus();
+    double best = 1e300;
+    bq_launch bestL = L;
+    auto trial = [&](int wgs, int b, double* out_ms) -> bq_status {
+        bq_launch t = L;
+        t.wg_count = wgs;
+        t.ticket_batch = b;
+        double tmin = 1e300;
+        for (int r = 0; r < reps; ++r) {
+            int32_t neg = 0;
+            bq_status st = sssp_bf(c, n, m, d_offsets, d_cols, d_w, src, d_dist, nullptr, &neg,
+                                   &t, stream);
+            if (st != BQ_OK) return st;
+            if (c->last.ms < tmin) tmin = c->last.ms;
+        }
+        *out_ms = tmin;
+        if (tmin < best) {
+            best = tmin;
+            bestL = t;
+        }
+        return BQ_OK;
+    };
+    // workgroup count: powers of two upwards until clearly past the minimum
+    int best_wgs = 4;
+    for (int wgs = 4; wgs <= max_grid; wgs *= 2) {
+        double ms = 0;
+        bq_status st = trial(wgs, 1, &ms);
+        if (st != BQ_OK) return st;
+        if (ms <= best) best_wgs = wgs;
+        if (ms > 2.0 * best && wgs >= 4 * best_wgs) break;
+        if (wgs * 2 > max_grid && wgs != max_grid) {
+            st = trial(max_grid, 1, &ms);
+            if (st != BQ_OK) return st;
+        }
+    }
+    // ticket batch at the best count and its neighbours
+    for (int b = 2; b <= 4; b *= 2) {
+        for (int f = -1; f <= 1; ++f) {
+            int wgs = f < 0 ? best_wgs / 2 : (f > 0 ? best_wgs * 2 : best_wgs);
+            if (wgs < 1 || wgs > max_grid) continue;
+            double ms = 0;
+            bq_status st = trial(wgs, b, &ms);
+            if (st != BQ_OK) return st;
+        }
+    }
+    *h_best = bestL;
+    *h_best_ms = best;
+    return BQ_OK;
+}
+
+int32_t sssp_last_trace(const sssp_ctx* c, uint64_t* h_out, int32_t cap_samples) {
+    if (!c || !h_out || cap_samples < 0) return BQ_EINVAL;
+    int k = c->trace_n < cap_samples ? c->trace_n : cap_samples;
+    for (int i = 0; i < 4 * k; ++i) h_out[i] = c->h_trace[i];
+    return k;
 }
 
 bq_status sssp_last_stats(const sssp_ctx* c, sssp_stats* out) {
@@ -775,6 +935,18 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     a.chunk_log = c->chunk_log;
     a.limit = L.limit;
     a.deadline = 10ull * L.limit;
+    a.trace = nullptr;
+    a.trace_shift = 0;
+    a.trace_cap = TRACE_CAP;
+    if (L.flags & BQ_F_TRACE) {
+        // about 256 samples per n + m/C items of work
+        unsigned long long unit = (unsigned long long)n + ((unsigned long long)m >> c->chunk_log);
+        unsigned sh = 0;
+        while ((1ull << (sh + 8)) < unit) ++sh;
+        a.trace = c->trace;
+        a.trace_shift = sh;
+        BQ_HIP_TRY(hipMemsetAsync(c->trace, 0xff, sizeof(unsigned long long) * 4 * TRACE_CAP, s));
+    }
 
     BQ_HIP_TRY(hipEventRecord(c->ev0, s));
     hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, s, q, (int)src);
@@ -799,6 +971,12 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     BQ_HIP_TRY(hipGetLastError());
     BQ_HIP_TRY(hipEventRecord(c->ev1, s));
     BQ_HIP_TRY(hipMemcpyAsync(c->h_ctrl, c->ctrl, sizeof(bq::Ctrl), hipMemcpyDeviceToHost, s));
+    c->trace_n = 0;
+    if (a.trace) {
+        BQ_HIP_TRY(hipMemcpyAsync(c->h_trace, c->trace, sizeof(unsigned long long) * 4 * TRACE_CAP,
+                                  hipMemcpyDeviceToHost, s));
+        c->trace_n = TRACE_CAP;
+    }
     BQ_HIP_TRY(hipStreamSynchronize(s));
     const bq::Ctrl* h = c->h_ctrl;
     float ms = 0.f, sms = 0.f;
@@ -811,6 +989,8 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     c->last.batches = h->stats[bq::ST_BATCH].v;
     c->last.walks = h->stats[bq::ST_WALK].v;
     c->last.improvements = h->stats[bq::ST_IMPROVE].v;
+    c->last.idle_polls = h->stats[bq::ST_POLL].v;
+    c->last.ticket_spins = h->stats[bq::ST_SPIN].v;
     c->last.ms = ms;
     c->last.solve_ms = sms;
     c->last.grid = grid;

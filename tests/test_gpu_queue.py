@@ -111,6 +111,7 @@ def test_many_waves_exact_multiset():
 
 
 def _mixed(cap, n_ops, launch=None):
+    b = (launch or {}).get("ticket_batch", 1)
     print(f"[queue] mixed cap={cap} n_ops={n_ops} launch={launch}", flush=True)
     q = pkg.Queue(cap)
     st, el, dl = q.bench_mixed(n_ops, launch=launch, log=True)
@@ -120,12 +121,14 @@ def _mixed(cap, n_ops, launch=None):
     el, dl = el.cpu().numpy(), dl.cpu().numpy()
     history.check_positions(el, dl, half)
     history.check_conservation(np.arange(half), dl, np.zeros(0))
-    # producer of value i: lane i % 64 of enqueuer wave (i // 64) % W; its
-    # sequence number is i // (64 W). Recode values as (producer, seq).
+    # value i: chunk c = i // K of enqueuer wave c % W, lane (i % K) % 64,
+    # that lane's item (c // W) * b + (i % K) // 64. Recode as (producer, seq).
     W = st["enq_waves"]
+    K = 64 * b
     i = el.astype(np.int64)
-    prod = ((i // 64) % W) * 64 + (i % 64)
-    seq = i // (64 * W)
+    c = i // K
+    prod = (c % W) * 64 + (i % K) % 64
+    seq = (c // W) * b + (i % K) // 64
     history.check_producer_fifo((prod << 20) | seq, 20)
     h, t, c = q.counters()
     history.check_quiescent(h, t, c, cap)
@@ -139,8 +142,15 @@ def test_mixed_small(cap):
 
 
 @pytest.mark.parametrize("wgs,wgsize", [(2, 64), (8, 256), (64, 512)])
-def test_mixed_shapes(wgs, wgsize):
-    _mixed(1024, 1 << 18, {"wg_count": wgs, "wg_size": wgsize})
+@pytest.mark.parametrize("b", [1, 4, 16])
+def test_mixed_shapes(wgs, wgsize, b):
+    _mixed(1024, 1 << 18, {"wg_count": wgs, "wg_size": wgsize, "ticket_batch": b})
+
+
+@pytest.mark.parametrize("b", [2, 8])
+def test_mixed_batch_tiny_capacity(b):
+    """K = 64*b items per ticket with a queue only a few chunks deep."""
+    _mixed(64 * b * 2, 1 << 18, {"ticket_batch": b})
 
 
 def test_mixed_full_size():
