@@ -116,6 +116,13 @@ def run_probes(pkg, torch, dev):
     pkg.probe(2, word, None, ops_per_lane=opl, grid=grid, block=block)
     ms = min(pkg.probe(2, word, None, ops_per_lane=opl, grid=grid, block=block) for _ in range(3))
     res["atomic_add_one_word_Mops"] = round(grid * block * opl / ms / 1e3, 1)
+    for kind, name in ((3, "atomic_add_one_word_leader_Mops"), (4, "load_one_word_leader_Mops")):
+        for grid in (256, 1024, 4096):
+            opl = 64
+            pkg.probe(kind, word, None, ops_per_lane=opl, grid=grid, block=256)
+            ms = min(pkg.probe(kind, word, None, ops_per_lane=opl, grid=grid, block=256)
+                     for _ in range(3))
+            res[f"{name}_w{grid * 4}"] = round(grid * 4 * opl / ms / 1e3, 1)
     return res
 
 

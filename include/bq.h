@@ -60,6 +60,10 @@ typedef struct {
     uint64_t timeout_us;  /* watchdog for a single wait; 0 = 2 s. A solve
                              running longer than 10x this is stopped too
                              (BQ_ETIMEOUT), so no launch runs unbounded. */
+    int32_t row_chunk;    /* solver: rows longer than this many edges are split
+                             into queue items of this size (power of two,
+                             64..65536); 0 = 1024 */
+    int32_t reserved;
 } bq_launch;
 
 #define BQ_F_VALIDATE 1u  /* sssp_bf: check the CSR on the device first */
@@ -186,8 +190,9 @@ bq_status sssp_bf(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
 
 /* Autotuner: time sssp_bf on this input (d_dist is used as scratch) for
  * workgroup counts 4, 8, 16, ... up to the co-resident maximum (stopping
- * once clearly past the fastest) and then ticket batches b = 2, 4 around
- * the fastest count; `reps` runs per candidate (the fastest counts).
+ * once clearly past the fastest), then ticket batches b = 2, 4 around the
+ * fastest count, then row chunks 256 and 4096 at the fastest shape; `reps`
+ * runs per candidate (the fastest counts).
  * *h_best gets the fastest launch (other fields copied from `base`, which
  * may be NULL), *h_best_ms its time. Synchronous. */
 bq_status sssp_autotune(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
@@ -217,7 +222,9 @@ int32_t sssp_last_trace(const sssp_ctx* ctx, uint64_t* h_out, int32_t cap_sample
  *          64-bit atomicMin at random slots of the int64 table d_a of `size`
  *          words (power of two); d_b: 8 bytes of scratch;
  *  kind 2: grid*block lanes each do ops_per_lane atomicAdd on the single
- *          uint64 d_a[0] (16 bytes needed).
+ *          uint64 d_a[0] (16 bytes needed);
+ *  kind 3: like kind 2 but one lane per wave (the leader-lane pattern);
+ *  kind 4: one lane per wave, ops_per_lane agent-scope loads of d_a[0].
  * *h_ms receives the kernel time. */
 bq_status bq_probe(int32_t kind, void* d_a, void* d_b, uint64_t size, uint64_t ops_per_lane,
                    int32_t grid, int32_t block, double* h_ms, void* stream);

@@ -39,7 +39,8 @@ class BQError(RuntimeError):
 class Launch(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("wg_count", ctypes.c_int32),
                 ("ticket_batch", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("timeout_us", ctypes.c_uint64)]
+                ("timeout_us", ctypes.c_uint64), ("row_chunk", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class BenchStats(ctypes.Structure):

@@ -26,6 +26,7 @@ struct Launch {
     int wg_size;
     int wg_count;
     int batch;                 // ticket_batch b
+    int row_chunk;             // solver row chunk (edges)
     uint32_t flags;
     unsigned long long limit;  // watchdog, 100 MHz ticks
 };

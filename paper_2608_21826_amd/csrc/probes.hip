@@ -53,6 +53,26 @@ __global__ void k_probe_atomic_add1(unsigned long long* word, unsigned long long
     if (acc == 1ull) word[1] = acc;
 }
 
+// one lane per wave: ops_per_lane atomicAdds on one word (the pattern of a
+// queue's control words, where a wave's leader lane does the atomic)
+__global__ void k_probe_atomic_add1_leader(unsigned long long* word,
+                                           unsigned long long ops_per_lane) {
+    if ((threadIdx.x & 63u) != 0u) return;
+    unsigned long long acc = 0;
+    for (unsigned long long i = 0; i < ops_per_lane; ++i)
+        acc += __hip_atomic_fetch_add(word, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (acc == 1ull) word[1] = acc;
+}
+
+// one lane per wave: ops_per_lane agent-scope loads of one word
+__global__ void k_probe_load1_leader(unsigned long long* word, unsigned long long ops_per_lane) {
+    if ((threadIdx.x & 63u) != 0u) return;
+    unsigned long long acc = 0;
+    for (unsigned long long i = 0; i < ops_per_lane; ++i)
+        acc += __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + i;
+    if (acc == 1ull) word[1] = acc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -81,6 +101,14 @@ bq_status bq_probe(int32_t kind, void* d_a, void* d_b, uint64_t size, uint64_t o
         }
         case 2:  // single contended word (needs 2 words of space)
             hipLaunchKernelGGL(k_probe_atomic_add1, dim3(grid), dim3(block), 0, s,
+                               (unsigned long long*)d_a, (unsigned long long)ops_per_lane);
+            break;
+        case 3:  // one lane per wave, atomicAdd on the single word d_a[0]
+            hipLaunchKernelGGL(k_probe_atomic_add1_leader, dim3(grid), dim3(block), 0, s,
+                               (unsigned long long*)d_a, (unsigned long long)ops_per_lane);
+            break;
+        case 4:  // one lane per wave, agent-scope loads of d_a[0]
+            hipLaunchKernelGGL(k_probe_load1_leader, dim3(grid), dim3(block), 0, s,
                                (unsigned long long*)d_a, (unsigned long long)ops_per_lane);
             break;
         default:

@@ -55,6 +55,10 @@ constexpr long long KEY_INF = 0x7FFFFFFFFFFFFFFELL;  // d = max, parent = all on
 constexpr int SOLVE_WG = 256;
 constexpr int WAVES_PER_WG = SOLVE_WG / 64;
 constexpr int OUTCAP = 1024;  // LDS push buffer per wave
+#ifndef SSSP_UNROLL
+#define SSSP_UNROLL 8
+#endif
+constexpr int U = SSSP_UNROLL;  // edges per lane per pipelined step
 
 struct SolveArgs {
     Queue q;
@@ -63,6 +67,7 @@ struct SolveArgs {
     const int* w;
     long long* key;          // the caller's dist buffer, used as key array
     unsigned* chunk_owner;   // [m >> chunk_log + 1]
+    const int* wrange;       // per-block (min w, max w) from k_init
     int n;
     int src;
     long long m;
@@ -80,32 +85,15 @@ __device__ __forceinline__ long long pack_key(long long d, unsigned parent, unsi
 }
 
 // ---------------------------------------------------------------------------
-// init: control block (1 block) and keys + weight range (grid-stride)
+// init: keys, the per-block weight range, and (block 0) the control block
+// with the source already enqueued
 // ---------------------------------------------------------------------------
-__global__ void k_init_ctrl(Queue q, int src) {
-    if (threadIdx.x != 0) return;
-    bq::Ctrl* c = q.ctrl;
-    c->pending.v = 1ull;
-    c->abort.v = 0ull;
-    c->error.v = 0ull;
-    c->negcycle.v = 0ull;
-    c->aux[0].v = (unsigned long long)(long long)INT_MAX;  // min w
-    c->aux[1].v = (unsigned long long)(long long)INT_MIN;  // max w
-    c->aux[2].v = c->head.v;                               // dequeue position at start
-    c->aux[4].v = bq::now_ticks();                         // clock at start
-    for (int i = 0; i < bq::ST_N; ++i) c->stats[i].v = 0ull;
-    // enqueue src: the queue is quiescent, so slot (tail mod N) is free for
-    // this round (ticket 2r) and count is 0
-    const unsigned long long pos = c->tail.v;
-    const unsigned slot = (unsigned)(pos & (q.N - 1ull));
-    const unsigned round = (unsigned)(pos >> q.logN);
-    q.slots[slot] = bq::slot_word(2u * round + 1u, (unsigned)src);
-    c->tail.v = pos + 1ull;
-    c->count.v = 1ull;
-}
+constexpr int INIT_WG = 256;
+constexpr int INIT_MAX_BLOCKS = 1024;
 
-__global__ void k_init_keys(long long* key, int n, int src, unsigned shift, const int* w,
-                            long long m, bq::Ctrl* ctrl) {
+__global__ __launch_bounds__(INIT_WG) void k_init(Queue q, long long* key, int n, int src,
+                                                  unsigned shift, const int* w, long long m,
+                                                  int* wrange /* [2 * gridDim.x] */) {
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
     const long long srckey = pack_key(0, (1u << (shift - 1u)) - 1u, shift);
@@ -117,16 +105,42 @@ __global__ void k_init_keys(long long* key, int n, int src, unsigned shift, cons
         hi = x > hi ? x : hi;
     }
     for (int off = 32; off > 0; off >>= 1) {
-        const int a = __shfl_xor(lo, off, 64), b = __shfl_xor(hi, off, 64);
-        lo = a < lo ? a : lo;
-        hi = b > hi ? b : hi;
+        const int a2 = __shfl_xor(lo, off, 64), b2 = __shfl_xor(hi, off, 64);
+        lo = a2 < lo ? a2 : lo;
+        hi = b2 > hi ? b2 : hi;
     }
-    if (bq::lane_id() == 0 && m > 0) {
-        __hip_atomic_fetch_min((long long*)&ctrl->aux[0].v, (long long)lo, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_max((long long*)&ctrl->aux[1].v, (long long)hi, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+    __shared__ int slo[INIT_WG / 64], shi[INIT_WG / 64];
+    if (bq::lane_id() == 0) {
+        slo[threadIdx.x >> 6] = lo;
+        shi[threadIdx.x >> 6] = hi;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < INIT_WG / 64; ++i) {
+            lo = slo[i] < lo ? slo[i] : lo;
+            hi = shi[i] > hi ? shi[i] : hi;
+        }
+        wrange[2 * blockIdx.x] = lo;
+        wrange[2 * blockIdx.x + 1] = hi;
+    }
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    bq::Ctrl* c = q.ctrl;
+    c->pending.v = 1ull;
+    c->abort.v = 0ull;
+    c->error.v = 0ull;
+    c->negcycle.v = 0ull;
+    c->aux[0].v = (unsigned long long)gridDim.x;  // number of weight-range partials
+    c->aux[2].v = c->head.v;                      // dequeue position at start
+    c->aux[4].v = bq::now_ticks();                // clock at start
+    for (int i = 0; i < bq::ST_N; ++i) c->stats[i].v = 0ull;
+    // enqueue src: the queue is quiescent, so slot (tail mod N) is free for
+    // this round (ticket 2r) and count is 0
+    const unsigned long long pos = c->tail.v;
+    const unsigned slot = (unsigned)(pos & (q.N - 1ull));
+    const unsigned round = (unsigned)(pos >> q.logN);
+    q.slots[slot] = bq::slot_word(2u * round + 1u, (unsigned)src);
+    c->tail.v = pos + 1ull;
+    c->count.v = 1ull;
 }
 
 // CSR checks (flag BQ_F_VALIDATE): aux[3] becomes non-zero on a defect.
@@ -376,8 +390,23 @@ __global__ __launch_bounds__(SOLVE_WG) void k_solve(SolveArgs a) {
     const unsigned n = (unsigned)a.n;
 
     // weight range -> packing precondition and the negative-cycle bound
-    const long long wmin = (long long)bq::ld_rlx(&q.ctrl->aux[0].v);
-    const long long wmax = (long long)bq::ld_rlx(&q.ctrl->aux[1].v);
+    long long wmin = INT_MAX, wmax = INT_MIN;
+    {
+        const int parts = (int)bq::ld_rlx(&q.ctrl->aux[0].v);
+        int lo = INT_MAX, hi = INT_MIN;
+        for (int i = lane; i < parts; i += 64) {
+            const int x = a.wrange[2 * i], y = a.wrange[2 * i + 1];
+            lo = x < lo ? x : lo;
+            hi = y > hi ? y : hi;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const int x = __shfl_xor(lo, off, 64), y = __shfl_xor(hi, off, 64);
+            lo = x < lo ? x : lo;
+            hi = y > hi ? y : hi;
+        }
+        wmin = lo;
+        wmax = hi;
+    }
     const unsigned long long head0 = bq::ld_rlx(&q.ctrl->aux[2].v);
     long long maxabs = 0;
     if (a.m > 0) {
@@ -545,38 +574,78 @@ __global__ __launch_bounds__(SOLVE_WG) void k_solve(SolveArgs a) {
         __builtin_amdgcn_wave_barrier();
 
         // ---- scan the concatenated edge range ---------------------------
+        // Three-stage software pipeline over groups of 64*U edges: in each
+        // step the wave issues the atomics of group g, the key loads of group
+        // g+1 and the target/weight loads of group g+2, and waits once.
+        // An atomicMin is issued only when the candidate is below the key
+        // loaded one step earlier: keys only decrease, so a candidate that is
+        // not below an earlier value of the key cannot change it, and the
+        // atomic would be a no-op. Most relaxations are such no-ops, and on
+        // high in-degree targets the atomics would otherwise serialize.
         const int total = carry;
         st_relax += (unsigned long long)total;
         int nout = 0;
-        for (int t0 = 0; t0 < total && ok; t0 += 256) {
-            long long cand[4];
-            int tv[4];
-            long long cd[4];
-            bool valid[4];
+        int av[U], aw[U], aidx[U];           // group g+2: target, weight, item
+        int bv[U], bw[U], bidx[U];           // group g+1
+        long long bkey[U];
+        auto fetch = [&](int t0) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int r = 0; r < U; ++r) {
                 const int t = t0 + r * 64 + lane;
-                valid[r] = t < total;
-                tv[r] = 0;
-                cand[r] = 0;
-                cd[r] = 0;
-                if (valid[r]) {
+                av[r] = -1;
+                aw[r] = 0;
+                aidx[r] = 0;
+                if (t < total) {
                     const int idx = find_item(L.pre, (int)e, t);
                     const long long edge = L.eb[idx] + (t - L.pre[idx]);
-                    tv[r] = a.col[edge];
-                    cd[r] = L.du[idx] + (long long)a.w[edge];
-                    cand[r] = pack_key(cd[r], (unsigned)L.u[idx], shift);
+                    aidx[r] = idx;
+                    av[r] = a.col[edge];
+                    aw[r] = a.w[edge];
                 }
             }
-            long long old[4];
+        };
+        // a batch that fits one step skips the key check: there the extra
+        // load would only add a round trip
+        const bool check = total > 64 * U;
+        auto advance = [&]() {  // stage A -> stage B, issuing B's key loads
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                old[r] = valid[r] ? __hip_atomic_fetch_min(&a.key[tv[r]], cand[r], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT)
-                                  : LLONG_MIN;
+            for (int r = 0; r < U; ++r) {
+                bv[r] = av[r];
+                bw[r] = aw[r];
+                bidx[r] = aidx[r];
+                bkey[r] = bv[r] < 0 ? LLONG_MIN
+                                    : (check ? bq::ld_rlx(&a.key[bv[r]]) : LLONG_MAX);
+            }
+        };
+        fetch(0);
+        advance();
+        if (64 * U < total) fetch(64 * U);
+        for (int t0 = 0; t0 < total && ok; t0 += 64 * U) {
+            long long cand[U], cd[U], seen[U];
+            int tv[U];
+            bool valid[U];
+#pragma unroll
+            for (int r = 0; r < U; ++r) {
+                tv[r] = bv[r];
+                valid[r] = tv[r] >= 0;
+                seen[r] = bkey[r];
+                cd[r] = L.du[bidx[r]] + (long long)bw[r];
+                cand[r] = pack_key(cd[r], (unsigned)L.u[bidx[r]], shift);
+            }
+            if (t0 + 64 * U < total) advance();
+            if (t0 + 128 * U < total) fetch(t0 + 128 * U);
+            long long old[U];
+#pragma unroll
+            for (int r = 0; r < U; ++r) {
+                const bool try_it = valid[r] && cand[r] < seen[r];
+                valid[r] = try_it;
+                old[r] = try_it ? __hip_atomic_fetch_min(&a.key[tv[r]], cand[r], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)
+                                : LLONG_MIN;
+            }
             bool neg = false;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int r = 0; r < U; ++r) {
                 const bool won = valid[r] && cand[r] < old[r];
                 const bool dropped = won && cd[r] < (old[r] >> shift);
                 st_impr += dropped;
@@ -594,7 +663,7 @@ __global__ __launch_bounds__(SOLVE_WG) void k_solve(SolveArgs a) {
                 ok = false;
                 break;
             }
-            if (nout > OUTCAP - 256) {
+            if (nout > OUTCAP - 64 * U) {
                 __builtin_amdgcn_wave_barrier();
                 if (!flush_out(a, L, nout, 0, false, spins)) {
                     ok = false;
@@ -671,6 +740,7 @@ struct sssp_ctx {
     unsigned long long* slots;
     bq::Ctrl* ctrl;
     unsigned* chunk_owner;
+    int* wrange;                  // [2 * INIT_MAX_BLOCKS]
     unsigned long long* trace;    // [4 * TRACE_CAP]
     unsigned long long* h_trace;  // pinned copy
     int trace_n;
@@ -685,6 +755,8 @@ struct sssp_ctx {
 namespace {
 
 constexpr unsigned DEFAULT_CHUNK_LOG = 10;  // rows longer than 1024 edges are split
+constexpr unsigned MIN_CHUNK_LOG = 6;       // smallest row chunk a launch may ask for
+constexpr unsigned MAX_CHUNK_LOG = 16;
 constexpr int TRACE_CAP = 4096;
 
 bq_status ctx_reset_queue(sssp_ctx* c, hipStream_t s) {
@@ -760,9 +832,10 @@ bq_status sssp_ctx_create(int32_t max_n, int64_t max_m, sssp_ctx** out) {
     c->max_m = max_m;
     c->chunk_log = DEFAULT_CHUNK_LOG;
     // items in the queue: at most n vertices (one per vertex, the q bit) plus
-    // chunk items; capacity 2 * pow2(n + m/C), at least 4096
+    // chunk items (at most m / C per fan-out generation); capacity
+    // 2 * pow2(n + m / C_min), at least 4096
     const unsigned long long need =
-        (unsigned long long)max_n + ((unsigned long long)max_m >> c->chunk_log) + 1ull;
+        (unsigned long long)max_n + ((unsigned long long)max_m >> MIN_CHUNK_LOG) + 1ull;
     unsigned long long cap = 4096ull;
     while (cap < 2ull * need) cap <<= 1;
     if (cap > (1ull << 31)) {
@@ -771,13 +844,14 @@ bq_status sssp_ctx_create(int32_t max_n, int64_t max_m, sssp_ctx** out) {
     }
     c->capacity = (uint32_t)cap;
     c->logN = bqh::log2_exact(cap);
-    const size_t chunks = (size_t)((unsigned long long)max_m >> c->chunk_log) + 1;
+    const size_t chunks = (size_t)((unsigned long long)max_m >> MIN_CHUNK_LOG) + 1;
     if (hipMalloc(&c->slots, sizeof(unsigned long long) * cap) != hipSuccess ||
         hipMalloc(&c->trace, sizeof(unsigned long long) * 4 * TRACE_CAP) != hipSuccess ||
         hipHostMalloc(&c->h_trace, sizeof(unsigned long long) * 4 * TRACE_CAP,
                       hipHostMallocDefault) != hipSuccess ||
         hipMalloc(&c->ctrl, sizeof(bq::Ctrl)) != hipSuccess ||
         hipMalloc(&c->chunk_owner, sizeof(unsigned) * chunks) != hipSuccess ||
+        hipMalloc(&c->wrange, sizeof(int) * 2 * INIT_MAX_BLOCKS) != hipSuccess ||
         hipHostMalloc(&c->h_ctrl, sizeof(bq::Ctrl), hipHostMallocDefault) != hipSuccess) {
         sssp_ctx_destroy(c);
         return BQ_ENOMEM;
@@ -804,6 +878,7 @@ bq_status sssp_ctx_destroy(sssp_ctx* c) {
     if (c->h_trace) (void)hipHostFree(c->h_trace);
     if (c->ctrl) (void)hipFree(c->ctrl);
     if (c->chunk_owner) (void)hipFree(c->chunk_owner);
+    if (c->wrange) (void)hipFree(c->wrange);
     if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -831,10 +906,11 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
     const int max_grid = per_cu * bqh::device_cus();
     double best = 1e300;
     bq_launch bestL = L;
-    auto trial = [&](int wgs, int b, double* out_ms) -> bq_status {
+    auto trial = [&](int wgs, int b, double* out_ms, int chunk = -1) -> bq_status {
         bq_launch t = L;
         t.wg_count = wgs;
         t.ticket_batch = b;
+        if (chunk >= 0) t.row_chunk = chunk;
         double tmin = 1e300;
         for (int r = 0; r < reps; ++r) {
             int32_t neg = 0;
@@ -873,6 +949,15 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
             if (st != BQ_OK) return st;
         }
     }
+    // row chunk around the default at the best shape so far
+    {
+        const bq_launch cur = bestL;
+        for (int chunk : {256, 4096}) {
+            double ms = 0;
+            bq_status st = trial(cur.wg_count, cur.ticket_batch, &ms, chunk);
+            if (st != BQ_OK) return st;
+        }
+    }
     *h_best = bestL;
     *h_best_ms = best;
     return BQ_OK;
@@ -898,8 +983,15 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     if (n < 1 || m < 0 || src < 0 || src >= n) return BQ_EINVAL;
     if (m > 0 && (!d_cols || !d_w)) return BQ_EINVAL;
     if (n > c->max_n || m > c->max_m) return BQ_EBUSY;
+    unsigned clog = DEFAULT_CHUNK_LOG;
+    if (launch && launch->row_chunk > 0) {
+        const int rc = launch->row_chunk;
+        if (rc & (rc - 1)) return BQ_EINVAL;
+        clog = bqh::log2_exact((unsigned long long)rc);
+        if (clog < MIN_CHUNK_LOG || clog > MAX_CHUNK_LOG) return BQ_EINVAL;
+    }
     // items are vertex ids below n and chunk ids n + j; both must fit 32 bits
-    if ((unsigned long long)n + ((unsigned long long)m >> c->chunk_log) + 1ull >= 0xFFFFFFFFull)
+    if ((unsigned long long)n + ((unsigned long long)m >> clog) + 1ull >= 0xFFFFFFFFull)
         return BQ_EINVAL;
     hipStream_t s = bqh::as_stream(stream);
     bqh::Launch L = bqh::resolve(launch, 0);
@@ -928,11 +1020,12 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     a.w = (const int*)d_w;
     a.key = (long long*)d_dist;
     a.chunk_owner = c->chunk_owner;
+    a.wrange = c->wrange;
     a.n = n;
     a.src = src;
     a.m = (long long)m;
     a.shift = shift;
-    a.chunk_log = c->chunk_log;
+    a.chunk_log = clog;
     a.limit = L.limit;
     a.deadline = 10ull * L.limit;
     a.trace = nullptr;
@@ -940,7 +1033,7 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     a.trace_cap = TRACE_CAP;
     if (L.flags & BQ_F_TRACE) {
         // about 256 samples per n + m/C items of work
-        unsigned long long unit = (unsigned long long)n + ((unsigned long long)m >> c->chunk_log);
+        unsigned long long unit = (unsigned long long)n + ((unsigned long long)m >> clog);
         unsigned sh = 0;
         while ((1ull << (sh + 8)) < unit) ++sh;
         a.trace = c->trace;
@@ -949,13 +1042,16 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     }
 
     BQ_HIP_TRY(hipEventRecord(c->ev0, s));
-    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, s, q, (int)src);
-    BQ_HIP_TRY(hipGetLastError());
-    const long long big = m > n ? m : n;
-    hipLaunchKernelGGL(k_init_keys, dim3(grid_for((int)(big > INT_MAX ? INT_MAX : big))), dim3(256),
-                       0, s, (long long*)d_dist, n, src, shift, (const int*)d_w, (long long)m,
-                       c->ctrl);
-    BQ_HIP_TRY(hipGetLastError());
+    {
+        const long long big = m > n ? m : n;
+        long long blocks = (big + (long long)INIT_WG * 8 - 1) / ((long long)INIT_WG * 8);
+        if (blocks < 1) blocks = 1;
+        if (blocks > INIT_MAX_BLOCKS) blocks = INIT_MAX_BLOCKS;
+        hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(INIT_WG), 0, s, q,
+                           (long long*)d_dist, n, src, shift, (const int*)d_w, (long long)m,
+                           c->wrange);
+        BQ_HIP_TRY(hipGetLastError());
+    }
     int grid = 0;
     bq_status st;
     BQ_HIP_TRY(hipEventRecord(c->evs0, s));
