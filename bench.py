@@ -135,6 +135,8 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="also run a 1 GiB copy kernel (byte-counter calibration)")
     ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--sssp-launch", type=str, default=None,
+                    help='fixed solver launch as JSON, e.g. {"wg_count":128,"row_chunk":256}')
     ap.add_argument("--no-tune", action="store_true",
                     help="library default launch shapes (no autotuning)")
     ap.add_argument("--sssp-only", action="store_true",
@@ -188,7 +190,9 @@ def main():
     # launch shapes, chosen before the timed region: the library's autotuner
     # for the solver, a small search over ticket batch / grid for the queue
     sssp_launch = {}
-    if not args.no_tune:
+    if args.sssp_launch:
+        sssp_launch = json.loads(args.sssp_launch)
+    elif not args.no_tune:
         sssp_launch, tune_ms = ctx.autotune(off, col, w, g.src, reps=2)
         log(f"sssp autotune: {sssp_launch} {tune_ms:.3f} ms")
     queue_launch = {"ticket_batch": 1}
