@@ -14,7 +14,8 @@
  *     Section III.C, whose input and output are those of Alg. 3 (graph G,
  *     source s -> distances d and the negative-cycle detection):
  *     sssp_ctx_create / sssp_ctx_destroy, sssp_bf (one query) and
- *     sssp_bf_batched (many queries in one persistent launch).
+ *     sssp_batch_create / sssp_bf_batched (many queries in one persistent
+ *     launch).
  *
  * Conventions for every call:
  *  - Pointers named d_* are device pointers (HBM of the current HIP device),
@@ -50,6 +51,7 @@ typedef enum {
 /* Opaque handles. */
 typedef struct bq_queue bq_queue;
 typedef struct sssp_ctx sssp_ctx;
+typedef struct sssp_batch sssp_batch;
 
 /* Launch shape. Zero fields mean "library default". */
 typedef struct {
@@ -63,11 +65,16 @@ typedef struct {
     int32_t row_chunk;    /* solver: rows longer than this many edges are split
                              into queue items of this size (power of two,
                              64..65536); 0 = 1024 */
-    int32_t reserved;
+    int32_t queue_scale;  /* batched solver: each query's queue holds
+                             pow2(queue_scale * (n + m/row_chunk + 1)) slots,
+                             1 or 2; 0 = 2 */
 } bq_launch;
 
 #define BQ_F_VALIDATE 1u  /* sssp_bf: check the CSR on the device first */
 #define BQ_F_TRACE 2u     /* sssp_bf: record a timeline (see sssp_last_trace) */
+#define BQ_F_GRAPH 4u     /* sssp_bf_batched: run the launch sequence as a hipGraph,
+                             captured on first use and replayed while the batch
+                             keeps its count and shape */
 
 /* Counters of one bq_bench_mixed run. */
 typedef struct {
@@ -93,7 +100,8 @@ typedef struct {
     int32_t wg_size;
 } sssp_stats;
 
-/* One query of sssp_bf_batched: all pointers are device pointers. */
+/* One query of sssp_bf_batched: all pointers are device pointers (the
+ * layouts and outputs of sssp_bf). */
 typedef struct {
     int32_t n;               /* vertices */
     int32_t src;             /* source vertex */
@@ -228,6 +236,41 @@ int32_t sssp_last_trace(const sssp_ctx* ctx, uint64_t* h_out, int32_t cap_sample
  * *h_ms receives the kernel time. */
 bq_status bq_probe(int32_t kind, void* d_a, void* d_b, uint64_t size, uint64_t ops_per_lane,
                    int32_t grid, int32_t block, double* h_ms, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many queries in one persistent launch
+ * ------------------------------------------------------------------------ */
+
+/* Workspace for batches of at most max_instances queries whose vertex and
+ * edge counts sum to at most max_total_n / max_total_m: one Broker Queue per
+ * query (slots + control block), chunk tables, the query table. */
+bq_status sssp_batch_create(int32_t max_instances, int64_t max_total_n, int64_t max_total_m,
+                            sssp_batch** out);
+bq_status sssp_batch_destroy(sssp_batch* b);
+
+/* Solve `count` independent queries (each its own CSR graph, source and
+ * outputs, all device pointers; graphs may be shared between queries) in one
+ * launch: every query gets the result sssp_bf would give it alone (dist,
+ * pred, h_neg_cycle[i]). Queries are ordered by size; persistent workgroups
+ * claim them biggest first, each query getting workgroups in proportion to
+ * its edges + vertices, and workgroups whose claims are used up join
+ * unfinished queries. With BQ_F_GRAPH the init / solve / unpack kernels run
+ * as one replayed hipGraph on the batch's own stream (ordered after the
+ * caller's stream). Synchronous. Errors: BQ_EINVAL (a bad query), BQ_EBUSY
+ * (batch larger than the workspace), BQ_ERANGE / BQ_ETIMEOUT (first failing
+ * query; others still have their results). */
+bq_status sssp_bf_batched(sssp_batch* b, int32_t count, const sssp_instance* h_inst,
+                          int32_t* h_neg_cycle, const bq_launch* launch, void* stream);
+
+/* Work counters (summed over the batch) and device time of the last call. */
+bq_status sssp_batch_last_stats(const sssp_batch* b, sssp_stats* h_out);
+
+/* Autotuner for a batch: workgroup counts 16, 32, ... up to the co-resident
+ * maximum, then row chunks 256 / 4096, ticket batch 2 and queue_scale 1 at
+ * the fastest shape; returns the fastest launch and its time. */
+bq_status sssp_batch_autotune(sssp_batch* b, int32_t count, const sssp_instance* h_inst,
+                              const bq_launch* base, int32_t reps, bq_launch* h_best,
+                              double* h_best_ms, void* stream);
 
 /* Text for a status code (static storage). */
 const char* bq_strerror(bq_status s);

@@ -20,12 +20,14 @@ LIB_PATH = os.path.join(HERE, "libbqsssp.so")
 BQ_OK, BQ_EINVAL, BQ_ENOMEM, BQ_EHIP, BQ_ERANGE, BQ_ETIMEOUT, BQ_EBUSY = 0, -1, -2, -3, -4, -5, -6
 BQ_F_VALIDATE = 1
 BQ_F_TRACE = 2
+BQ_F_GRAPH = 4
 
 # every symbol include/bq.h declares
 EXPORTS = [
     "bq_create", "bq_destroy", "bq_reset", "bq_enqueue", "bq_dequeue", "bq_counters",
     "bq_bench_mixed", "sssp_ctx_create", "sssp_ctx_destroy", "sssp_bf", "sssp_last_stats",
-    "sssp_last_trace", "sssp_autotune",
+    "sssp_last_trace", "sssp_autotune", "sssp_batch_create", "sssp_batch_destroy",
+    "sssp_bf_batched", "sssp_batch_last_stats", "sssp_batch_autotune",
     "bq_strerror", "bq_device_cus", "bq_probe",
 ]
 
@@ -40,7 +42,7 @@ class Launch(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("wg_count", ctypes.c_int32),
                 ("ticket_batch", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("timeout_us", ctypes.c_uint64), ("row_chunk", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("queue_scale", ctypes.c_int32)]
 
 
 class BenchStats(ctypes.Structure):
@@ -60,6 +62,12 @@ class SsspStats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("src", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p), ("cols", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("dist", ctypes.c_void_p), ("pred", ctypes.c_void_p)]
 
 
 _lib = None
@@ -96,6 +104,12 @@ def lib(path: str | None = None):
         "bq_strerror": ([i32], ctypes.c_char_p),
         "bq_device_cus": ([], i32),
         "bq_probe": ([i32, vp, vp, u64, u64, i32, i32, P(ctypes.c_double), vp], i32),
+        "sssp_batch_create": ([i32, i64, i64, P(vp)], i32),
+        "sssp_batch_destroy": ([vp], i32),
+        "sssp_bf_batched": ([vp, i32, P(Instance), P(i32), P(Launch), vp], i32),
+        "sssp_batch_last_stats": ([vp, P(SsspStats)], i32),
+        "sssp_batch_autotune": ([vp, i32, P(Instance), P(Launch), i32, P(Launch),
+                                 P(ctypes.c_double), vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -296,6 +310,67 @@ def sssp_bf(offsets, cols, w, src: int, want_pred=True, launch=None, validate=Tr
     finally:
         if own:
             ctx.close()
+
+
+class SsspBatch:
+    """sssp_bf_batched workspace: up to max_instances queries with at most
+    max_total_n vertices and max_total_m edges in total."""
+
+    def __init__(self, max_instances: int, max_total_n: int, max_total_m: int):
+        h = ctypes.c_void_p()
+        _check(lib().sssp_batch_create(int(max_instances), int(max_total_n), int(max_total_m),
+                                       ctypes.byref(h)), "sssp_batch_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().sssp_batch_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+    @staticmethod
+    def _table(queries):
+        """queries: list of (offsets, cols, w, src, dist, pred-or-None)."""
+        import torch
+        arr = (Instance * len(queries))()
+        for i, (off, col, w, src, dist, pred) in enumerate(queries):
+            n = off.numel() - 1
+            _need(off, torch.int64, "offsets", n + 1)
+            _need(col, torch.int32, "cols")
+            _need(w, torch.int32, "w", col.numel())
+            _need(dist, torch.int64, "dist", n)
+            if pred is not None:
+                _need(pred, torch.int32, "pred", n)
+            arr[i] = Instance(n, int(src), col.numel(), off.data_ptr(), col.data_ptr(),
+                              w.data_ptr(), dist.data_ptr(), pred.data_ptr() if pred is not None else 0)
+        return arr
+
+    def solve(self, queries, launch=None, graph=False, stream=None):
+        """Solve all queries; fills their dist/pred tensors, returns the list of
+        negative-cycle flags."""
+        arr = self._table(queries)
+        neg = (ctypes.c_int32 * len(queries))()
+        L = Launch(**(launch or {})) if not isinstance(launch, Launch) else launch
+        if graph:
+            L.flags |= BQ_F_GRAPH
+        _check(lib().sssp_bf_batched(self.handle, len(queries), arr, neg, ctypes.byref(L),
+                                     _stream(stream)), "sssp_bf_batched")
+        return [bool(x) for x in neg]
+
+    def autotune(self, queries, reps: int = 2, base=None, stream=None):
+        arr = self._table(queries)
+        best = Launch()
+        ms = ctypes.c_double()
+        _check(lib().sssp_batch_autotune(self.handle, len(queries), arr, _launch(base), int(reps),
+                                         ctypes.byref(best), ctypes.byref(ms), _stream(stream)),
+               "sssp_batch_autotune")
+        return {k: getattr(best, k) for k, _ in best._fields_}, ms.value
+
+    def stats(self) -> dict:
+        s = SsspStats()
+        _check(lib().sssp_batch_last_stats(self.handle, ctypes.byref(s)), "sssp_batch_last_stats")
+        return s.as_dict()
 
 
 def device_cus() -> int:

@@ -1,0 +1,610 @@
+// Batched form: many SSSP queries (different graphs and sources, uneven
+// sizes) in one persistent launch, each query with its own Broker Queue.
+//
+// Three kernels, the same for any batch of a given count, so the sequence
+// can be captured once in a hipGraph and replayed:
+//  k_binit   - per "unit" (a slice of one query's vertices and edges): keys,
+//              weight-range partials; a query's first unit also resets its
+//              control block and enqueues its source
+//  k_bsolve  - persistent workgroups claim queries from a claim list (queries
+//              sorted by size, each listed in proportion to its work, so big
+//              queries get several workgroups) and, when the list runs out,
+//              join any unfinished query; each runs the solver loop of the
+//              single-query launch on that query's queue
+//  k_bunpack - per unit: distances and predecessors; per query: the result
+//              flags
+#include <hip/hip_runtime.h>
+#include <limits.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "host_common.hpp"
+#include "sssp_device.hpp"
+
+namespace {
+
+constexpr unsigned BDEFAULT_CHUNK_LOG = 10;
+constexpr unsigned BMIN_CHUNK_LOG = 6;
+constexpr unsigned BMAX_CHUNK_LOG = 16;
+constexpr long long UNIT = 65536;  // vertices or edges per init/unpack unit
+constexpr int BINIT_WG = 256;
+
+struct InstDesc {
+    SolveArgs a;
+    int* pred;
+    int orig;        // index in the caller's array
+    int unit_begin;  // units [unit_begin, unit_end) belong to this query
+    int unit_end;
+    int pad;
+};
+
+struct Unit {
+    int inst;
+    int pad;
+    long long v0, v1, e0, e1;
+};
+
+struct BatchCtl {
+    bq::Word cursor;  // next claim-list entry
+    bq::Word stats[bq::ST_N];
+};
+
+__global__ __launch_bounds__(BINIT_WG) void k_binit(const InstDesc* D, const Unit* units,
+                                                    int n_units, int* partials, BatchCtl* bc) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        bc->cursor.v = 0ull;
+        for (int i = 0; i < bq::ST_N; ++i) bc->stats[i].v = 0ull;
+    }
+    __shared__ int slo[BINIT_WG / 64], shi[BINIT_WG / 64];
+    for (int u = blockIdx.x; u < n_units; u += gridDim.x) {
+        const Unit un = units[u];
+        const InstDesc& d = D[un.inst];
+        const SolveArgs& a = d.a;
+        const long long srckey = pack_key(0, (1u << (a.shift - 1u)) - 1u, a.shift);
+        for (long long v = un.v0 + threadIdx.x; v < un.v1; v += blockDim.x)
+            a.key[v] = (v == a.src) ? srckey : KEY_INF;
+        int lo = INT_MAX, hi = INT_MIN;
+        for (long long e = un.e0 + threadIdx.x; e < un.e1; e += blockDim.x) {
+            const int x = a.w[e];
+            lo = x < lo ? x : lo;
+            hi = x > hi ? x : hi;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const int x = __shfl_xor(lo, off, 64), y = __shfl_xor(hi, off, 64);
+            lo = x < lo ? x : lo;
+            hi = y > hi ? y : hi;
+        }
+        if (bq::lane_id() == 0) {
+            slo[threadIdx.x >> 6] = lo;
+            shi[threadIdx.x >> 6] = hi;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int i = 1; i < BINIT_WG / 64; ++i) {
+                lo = slo[i] < lo ? slo[i] : lo;
+                hi = shi[i] > hi ? shi[i] : hi;
+            }
+            partials[2 * u] = lo;
+            partials[2 * u + 1] = hi;
+            if (u == d.unit_begin) {
+                bq::Ctrl* c = a.q.ctrl;
+                c->pending.v = 1ull;
+                c->abort.v = 0ull;
+                c->error.v = 0ull;
+                c->negcycle.v = 0ull;
+                c->aux[0].v = (unsigned long long)(d.unit_end - d.unit_begin);
+                c->aux[2].v = c->head.v;
+                c->aux[4].v = bq::now_ticks();
+                c->aux[5].v = 0ull;  // finished flag
+                for (int i = 0; i < bq::ST_N; ++i) c->stats[i].v = 0ull;
+                const unsigned long long pos = c->tail.v;
+                const unsigned slot = (unsigned)(pos & (a.q.N - 1ull));
+                const unsigned round = (unsigned)(pos >> a.q.logN);
+                a.q.slots[slot] = bq::slot_word(2u * round + 1u, (unsigned)a.src);
+                c->tail.v = pos + 1ull;
+                c->count.v = 1ull;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int B>
+__global__ __launch_bounds__(SOLVE_WG) void k_bsolve(const InstDesc* D, int count,
+                                                     const int* claim, int n_claim,
+                                                     BatchCtl* bc) {
+    __shared__ WaveLds<B> lds[WAVES_PER_WG];
+    __shared__ WgShared S;
+    __shared__ int s_inst;
+    WaveLds<B>& L = lds[threadIdx.x >> 6];
+    const int wid = (int)(threadIdx.x >> 6);
+    WaveStats st{};
+    int help = (int)(blockIdx.x % (unsigned)count);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int i = -1;
+            const unsigned long long c = bq::add_rlx(&bc->cursor.v, 1ull);
+            if (c < (unsigned long long)n_claim) {
+                i = claim[c];
+            } else {
+                for (int k = 0; k < count; ++k) {
+                    const int j = (help + k) % count;
+                    if (bq::ld_rlx(&D[j].a.q.ctrl->aux[5].v) == 0ull) {
+                        i = j;
+                        break;
+                    }
+                }
+                if (i >= 0) help = (i + 1) % count;
+            }
+            s_inst = i;
+            S.poller = -1;
+            S.wake = 0u;
+            S.done = 0;
+        }
+        __syncthreads();
+        const int i = s_inst;
+        if (i < 0) break;
+        const SolveArgs a = D[i].a;
+        solve_instance<B>(a, L, S, wid, st);
+        __syncthreads();
+        if (threadIdx.x == 0) bq::st_rlx(&a.q.ctrl->aux[5].v, 1ull);
+        __syncthreads();
+    }
+    flush_stats(bc->stats, st);
+}
+
+__global__ void k_bunpack(const InstDesc* D, const Unit* units, int n_units,
+                          long long* results) {
+    for (int u = blockIdx.x; u < n_units; u += gridDim.x) {
+        const Unit un = units[u];
+        const InstDesc& d = D[un.inst];
+        const SolveArgs& a = d.a;
+        const long long dmax = KEY_INF >> a.shift;
+        const unsigned pmask = (1u << (a.shift - 1u)) - 1u;
+        for (long long v = un.v0 + threadIdx.x; v < un.v1; v += blockDim.x) {
+            const long long k = a.key[v];
+            const long long dd = k >> a.shift;
+            const bool reached = dd != dmax;
+            a.key[v] = reached ? dd : LLONG_MAX;
+            if (d.pred)
+                d.pred[v] = (reached && v != a.src)
+                                ? (int)(((unsigned long long)k >> 1) & pmask)
+                                : -1;
+        }
+        if (u == d.unit_begin && threadIdx.x == 0) {
+            const bq::Ctrl* c = a.q.ctrl;
+            results[d.orig] = (long long)(c->negcycle.v & 1ull) |
+                              ((long long)c->error.v << 8) | ((long long)c->abort.v << 16);
+        }
+    }
+}
+
+unsigned bkey_shift(int n) {
+    unsigned pb = 0;
+    while ((1ull << pb) < (unsigned long long)n + 1ull) ++pb;
+    return pb + 1u;
+}
+
+unsigned long long pow2ceil(unsigned long long x) {
+    unsigned long long p = 1ull;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+struct sssp_batch {
+    int device;
+    int max_inst;
+    long long max_n, max_m;
+    size_t slot_cap, chunk_cap, max_units, max_claim;
+    unsigned long long* slots;
+    unsigned* chunks;
+    bq::Ctrl* ctrls;
+    InstDesc* d_desc;
+    Unit* d_units;
+    int* d_claim;
+    int* d_partials;
+    long long* d_results;
+    BatchCtl* d_bc;
+    InstDesc* h_desc;
+    Unit* h_units;
+    int* h_claim;
+    long long* h_results;
+    BatchCtl* h_bc;
+    hipStream_t stream;
+    hipEvent_t ev0, ev1, ev_in;
+    std::vector<unsigned long long> layout;
+    bool dirty;
+    hipGraphExec_t exec;
+    hipGraph_t graph;
+    unsigned long long graph_key[8];
+    int per_cu[3];
+    sssp_stats last;
+};
+
+namespace {
+
+bq_status batch_launch_kernels(sssp_batch* b, int count, int n_units, int n_claim, int grid,
+                               int B) {
+    hipStream_t s = b->stream;
+    const int ug = n_units < 2048 ? n_units : 2048;
+    hipLaunchKernelGGL(k_binit, dim3(ug), dim3(BINIT_WG), 0, s, b->d_desc, b->d_units, n_units,
+                       b->d_partials, b->d_bc);
+    switch (B) {
+        case 64:
+            hipLaunchKernelGGL(k_bsolve<64>, dim3(grid), dim3(SOLVE_WG), 0, s, b->d_desc, count,
+                               b->d_claim, n_claim, b->d_bc);
+            break;
+        case 128:
+            hipLaunchKernelGGL(k_bsolve<128>, dim3(grid), dim3(SOLVE_WG), 0, s, b->d_desc, count,
+                               b->d_claim, n_claim, b->d_bc);
+            break;
+        default:
+            hipLaunchKernelGGL(k_bsolve<256>, dim3(grid), dim3(SOLVE_WG), 0, s, b->d_desc, count,
+                               b->d_claim, n_claim, b->d_bc);
+            break;
+    }
+    hipLaunchKernelGGL(k_bunpack, dim3(ug), dim3(256), 0, s, b->d_desc, b->d_units, n_units,
+                       b->d_results);
+    BQ_HIP_TRY(hipGetLastError());
+    return BQ_OK;
+}
+
+int batch_max_grid(sssp_batch* b, int B) {
+    const int slot = B == 64 ? 0 : (B == 128 ? 1 : 2);
+    int& pc = b->per_cu[slot];
+    if (pc == 0) {
+        hipError_t e;
+        if (B == 64)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, k_bsolve<64>, SOLVE_WG, 0);
+        else if (B == 128)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, k_bsolve<128>, SOLVE_WG, 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, k_bsolve<256>, SOLVE_WG, 0);
+        if (e != hipSuccess || pc < 1) pc = 1;
+    }
+    return pc * bqh::device_cus();
+}
+
+}  // namespace
+
+extern "C" {
+
+bq_status sssp_batch_create(int32_t max_instances, int64_t max_total_n, int64_t max_total_m,
+                            sssp_batch** out) {
+    if (!out || max_instances < 1 || max_total_n < 1 || max_total_m < 0) return BQ_EINVAL;
+    *out = nullptr;
+    sssp_batch* b = new sssp_batch();
+    BQ_HIP_TRY(hipGetDevice(&b->device));
+    b->max_inst = max_instances;
+    b->max_n = max_total_n;
+    b->max_m = max_total_m;
+    // per query: capacity pow2(scale * (n + m/C + 1)) with scale <= 2 and
+    // C >= 64, at least 4096 -> at most 4 * (n + m/64 + 1) + 4096 each
+    b->slot_cap = (size_t)(4 * (max_total_n + max_total_m / 64 + max_instances)) +
+                  (size_t)max_instances * 4096;
+    b->chunk_cap = (size_t)(max_total_m / 64 + max_instances);
+    b->max_units = (size_t)((max_total_n + max_total_m) / UNIT + 2 * max_instances);
+    b->max_claim = (size_t)(8 * 4096 + max_instances);
+    if (hipMalloc(&b->slots, sizeof(unsigned long long) * b->slot_cap) != hipSuccess ||
+        hipMalloc(&b->chunks, sizeof(unsigned) * b->chunk_cap) != hipSuccess ||
+        hipMalloc(&b->ctrls, sizeof(bq::Ctrl) * max_instances) != hipSuccess ||
+        hipMalloc(&b->d_desc, sizeof(InstDesc) * max_instances) != hipSuccess ||
+        hipMalloc(&b->d_units, sizeof(Unit) * b->max_units) != hipSuccess ||
+        hipMalloc(&b->d_claim, sizeof(int) * b->max_claim) != hipSuccess ||
+        hipMalloc(&b->d_partials, sizeof(int) * 2 * b->max_units) != hipSuccess ||
+        hipMalloc(&b->d_results, sizeof(long long) * max_instances) != hipSuccess ||
+        hipMalloc(&b->d_bc, sizeof(BatchCtl)) != hipSuccess ||
+        hipHostMalloc(&b->h_desc, sizeof(InstDesc) * max_instances, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(&b->h_units, sizeof(Unit) * b->max_units, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(&b->h_claim, sizeof(int) * b->max_claim, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(&b->h_results, sizeof(long long) * max_instances, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(&b->h_bc, sizeof(BatchCtl), hipHostMallocDefault) != hipSuccess) {
+        sssp_batch_destroy(b);
+        return BQ_ENOMEM;
+    }
+    BQ_HIP_TRY(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    BQ_HIP_TRY(hipEventCreate(&b->ev0));
+    BQ_HIP_TRY(hipEventCreate(&b->ev1));
+    BQ_HIP_TRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+    b->dirty = true;
+    BQ_HIP_TRY(hipMemsetAsync(b->slots, 0, sizeof(unsigned long long) * b->slot_cap, b->stream));
+    BQ_HIP_TRY(hipMemsetAsync(b->ctrls, 0, sizeof(bq::Ctrl) * max_instances, b->stream));
+    BQ_HIP_TRY(hipStreamSynchronize(b->stream));
+    b->dirty = false;
+    *out = b;
+    return BQ_OK;
+}
+
+bq_status sssp_batch_destroy(sssp_batch* b) {
+    if (!b) return BQ_OK;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->slots) (void)hipFree(b->slots);
+    if (b->chunks) (void)hipFree(b->chunks);
+    if (b->ctrls) (void)hipFree(b->ctrls);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->d_units) (void)hipFree(b->d_units);
+    if (b->d_claim) (void)hipFree(b->d_claim);
+    if (b->d_partials) (void)hipFree(b->d_partials);
+    if (b->d_results) (void)hipFree(b->d_results);
+    if (b->d_bc) (void)hipFree(b->d_bc);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
+    if (b->h_units) (void)hipHostFree(b->h_units);
+    if (b->h_claim) (void)hipHostFree(b->h_claim);
+    if (b->h_results) (void)hipHostFree(b->h_results);
+    if (b->h_bc) (void)hipHostFree(b->h_bc);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    delete b;
+    return BQ_OK;
+}
+
+bq_status sssp_batch_last_stats(const sssp_batch* b, sssp_stats* out) {
+    if (!b || !out) return BQ_EINVAL;
+    *out = b->last;
+    return BQ_OK;
+}
+
+bq_status sssp_bf_batched(sssp_batch* b, int32_t count, const sssp_instance* h_inst,
+                          int32_t* h_neg_cycle, const bq_launch* launch, void* stream) {
+    if (!b || !h_inst || !h_neg_cycle || count < 1) return BQ_EINVAL;
+    if (count > b->max_inst) return BQ_EBUSY;
+    bqh::Launch L = bqh::resolve(launch, 0);
+    if (L.batch != 1 && L.batch != 2 && L.batch != 4) return BQ_EINVAL;
+    const int B = 64 * L.batch;
+    unsigned clog = BDEFAULT_CHUNK_LOG;
+    if (L.row_chunk > 0) {
+        if (L.row_chunk & (L.row_chunk - 1)) return BQ_EINVAL;
+        clog = bqh::log2_exact((unsigned long long)L.row_chunk);
+        if (clog < BMIN_CHUNK_LOG || clog > BMAX_CHUNK_LOG) return BQ_EINVAL;
+    }
+    const int scale = (launch && launch->queue_scale > 0) ? launch->queue_scale : 2;
+    if (scale > 2) return BQ_EINVAL;
+    // validate and order by work, biggest first
+    long long tot_n = 0, tot_m = 0;
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) {
+        const sssp_instance& x = h_inst[i];
+        if (x.n < 1 || x.m < 0 || x.src < 0 || x.src >= x.n || !x.offsets || !x.dist)
+            return BQ_EINVAL;
+        if (x.m > 0 && (!x.cols || !x.w)) return BQ_EINVAL;
+        if ((unsigned long long)x.n + ((unsigned long long)x.m >> clog) + 1ull >= 0xFFFFFFFFull)
+            return BQ_EINVAL;
+        tot_n += x.n;
+        tot_m += x.m;
+        order[i] = i;
+    }
+    if (tot_n > b->max_n || tot_m > b->max_m) return BQ_EBUSY;
+    std::vector<long long> work(count);
+    for (int i = 0; i < count; ++i) work[i] = h_inst[i].m + h_inst[i].n;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+
+    const int max_grid = batch_max_grid(b, B);
+    int grid = L.wg_count > 0 ? L.wg_count : max_grid;
+    if (grid > max_grid) grid = max_grid;
+
+    // layout: queue slots, chunk tables, units, claim list
+    std::vector<unsigned long long> layout;
+    layout.reserve(2 * count + 2);
+    size_t slot_off = 0, chunk_off = 0;
+    int n_units = 0, n_claim = 0;
+    long long tot_work = 0;
+    for (int i = 0; i < count; ++i) tot_work += work[i];
+    for (int k = 0; k < count; ++k) {
+        const int i = order[k];
+        const sssp_instance& x = h_inst[i];
+        unsigned long long need =
+            (unsigned long long)x.n + ((unsigned long long)x.m >> clog) + 1ull;
+        unsigned long long cap = pow2ceil((unsigned long long)scale * need);
+        if (cap < 4096ull) cap = 4096ull;
+        const size_t chunks = (size_t)((unsigned long long)x.m >> clog) + 1;
+        const long long big = x.n > x.m ? x.n : x.m;
+        const int ku = (int)((big + UNIT - 1) / UNIT);
+        if (slot_off + cap > b->slot_cap || chunk_off + chunks > b->chunk_cap ||
+            (size_t)(n_units + ku) > b->max_units)
+            return BQ_EBUSY;
+        InstDesc& d = b->h_desc[k];
+        memset(&d, 0, sizeof d);
+        SolveArgs& a = d.a;
+        a.q.slots = b->slots + slot_off;
+        a.q.ctrl = b->ctrls + k;
+        a.q.logN = bqh::log2_exact(cap);
+        a.q.pad = 0;
+        a.q.N = cap;
+        a.off = (const long long*)x.offsets;
+        a.col = (const int*)x.cols;
+        a.w = (const int*)x.w;
+        a.key = (long long*)x.dist;
+        a.chunk_owner = b->chunks + chunk_off;
+        a.wrange = b->d_partials + 2 * n_units;
+        a.n = x.n;
+        a.src = x.src;
+        a.m = (long long)x.m;
+        a.shift = bkey_shift(x.n);
+        a.chunk_log = clog;
+        a.limit = L.limit;
+        a.deadline = 10ull * L.limit;
+        a.trace = nullptr;
+        a.trace_shift = 0;
+        a.trace_cap = 0;
+        d.pred = (int*)x.pred;
+        d.orig = i;
+        d.unit_begin = n_units;
+        for (int j = 0; j < ku; ++j) {
+            Unit& un = b->h_units[n_units + j];
+            un.inst = k;
+            un.pad = 0;
+            un.v0 = (long long)x.n * j / ku;
+            un.v1 = (long long)x.n * (j + 1) / ku;
+            un.e0 = (long long)x.m * j / ku;
+            un.e1 = (long long)x.m * (j + 1) / ku;
+        }
+        n_units += ku;
+        d.unit_end = n_units;
+        // workgroups in proportion to the query's share of the work
+        long long tgt = tot_work > 0 ? (long long)grid * work[i] / tot_work : 1;
+        if (tgt < 1) tgt = 1;
+        for (long long t = 0; t < tgt && (size_t)n_claim < b->max_claim; ++t)
+            b->h_claim[n_claim++] = k;
+        layout.push_back(cap);
+        layout.push_back(slot_off);
+        slot_off += cap;
+        chunk_off += chunks;
+    }
+    hipStream_t cs = bqh::as_stream(stream);
+    hipStream_t s = b->stream;
+    // queue state is reusable only if every query keeps the same slots and a
+    // clean end; otherwise zero the slots and control blocks first
+    if (b->dirty || layout != b->layout) {
+        BQ_HIP_TRY(hipMemsetAsync(b->slots, 0, sizeof(unsigned long long) * slot_off, s));
+        BQ_HIP_TRY(hipMemsetAsync(b->ctrls, 0, sizeof(bq::Ctrl) * count, s));
+        b->layout = layout;
+        b->dirty = false;
+    }
+    BQ_HIP_TRY(hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(InstDesc) * count,
+                              hipMemcpyHostToDevice, s));
+    BQ_HIP_TRY(hipMemcpyAsync(b->d_units, b->h_units, sizeof(Unit) * n_units,
+                              hipMemcpyHostToDevice, s));
+    BQ_HIP_TRY(hipMemcpyAsync(b->d_claim, b->h_claim, sizeof(int) * n_claim,
+                              hipMemcpyHostToDevice, s));
+    // the caller's stream must be done with the inputs
+    BQ_HIP_TRY(hipEventRecord(b->ev_in, cs));
+    BQ_HIP_TRY(hipStreamWaitEvent(s, b->ev_in, 0));
+
+    BQ_HIP_TRY(hipEventRecord(b->ev0, s));
+    if (L.flags & BQ_F_GRAPH) {
+        const unsigned long long key[8] = {(unsigned long long)count, (unsigned long long)n_units,
+                                           (unsigned long long)n_claim, (unsigned long long)grid,
+                                           (unsigned long long)B, 0, 0, 0};
+        if (!b->exec || memcmp(key, b->graph_key, sizeof key) != 0) {
+            if (b->exec) {
+                (void)hipGraphExecDestroy(b->exec);
+                b->exec = nullptr;
+            }
+            if (b->graph) {
+                (void)hipGraphDestroy(b->graph);
+                b->graph = nullptr;
+            }
+            BQ_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            bq_status st = batch_launch_kernels(b, count, n_units, n_claim, grid, B);
+            hipGraph_t g = nullptr;
+            hipError_t ce = hipStreamEndCapture(s, &g);
+            if (st != BQ_OK) return st;
+            BQ_HIP_TRY(ce);
+            b->graph = g;
+            BQ_HIP_TRY(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+            memcpy(b->graph_key, key, sizeof key);
+        }
+        BQ_HIP_TRY(hipGraphLaunch(b->exec, s));
+    } else {
+        bq_status st = batch_launch_kernels(b, count, n_units, n_claim, grid, B);
+        if (st != BQ_OK) return st;
+    }
+    BQ_HIP_TRY(hipEventRecord(b->ev1, s));
+    BQ_HIP_TRY(hipMemcpyAsync(b->h_results, b->d_results, sizeof(long long) * count,
+                              hipMemcpyDeviceToHost, s));
+    BQ_HIP_TRY(hipMemcpyAsync(b->h_bc, b->d_bc, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
+    BQ_HIP_TRY(hipStreamSynchronize(s));
+    float ms = 0.f;
+    BQ_HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    const BatchCtl* h = b->h_bc;
+    b->last = sssp_stats{};
+    b->last.dequeued = h->stats[bq::ST_DEQ].v;
+    b->last.relaxations = h->stats[bq::ST_RELAX].v;
+    b->last.pushes = h->stats[bq::ST_PUSH].v;
+    b->last.fanout = h->stats[bq::ST_FANOUT].v;
+    b->last.batches = h->stats[bq::ST_BATCH].v;
+    b->last.walks = h->stats[bq::ST_WALK].v;
+    b->last.improvements = h->stats[bq::ST_IMPROVE].v;
+    b->last.idle_polls = h->stats[bq::ST_POLL].v;
+    b->last.ticket_spins = h->stats[bq::ST_SPIN].v;
+    b->last.ms = ms;
+    b->last.solve_ms = ms;
+    b->last.grid = grid;
+    b->last.wg_size = SOLVE_WG;
+    bq_status ret = BQ_OK;
+    for (int i = 0; i < count; ++i) {
+        const long long r = b->h_results[i];
+        h_neg_cycle[i] = (int32_t)(r & 1);
+        const long long err = (r >> 8) & 0xff;
+        if (r & ~1ll) b->dirty = true;  // a stopped query leaves its queue non-quiescent
+        if (err == bq::ERR_RANGE && ret == BQ_OK) ret = BQ_ERANGE;
+        else if (err != 0 && ret == BQ_OK) ret = BQ_ETIMEOUT;
+    }
+    return ret;
+}
+
+bq_status sssp_batch_autotune(sssp_batch* b, int32_t count, const sssp_instance* h_inst,
+                              const bq_launch* base, int32_t reps, bq_launch* h_best,
+                              double* h_best_ms, void* stream) {
+    if (!b || !h_inst || !h_best || !h_best_ms || count < 1) return BQ_EINVAL;
+    if (reps < 1) reps = 2;
+    bq_launch L = {};
+    if (base) L = *base;
+    std::vector<int32_t> neg(count);
+    double best = 1e300;
+    bq_launch bestL = L;
+    auto trial = [&](bq_launch t) -> bq_status {
+        double tmin = 1e300;
+        for (int r = 0; r < reps; ++r) {
+            bq_status st = sssp_bf_batched(b, count, h_inst, neg.data(), &t, stream);
+            if (st != BQ_OK) return st;
+            if (b->last.ms < tmin) tmin = b->last.ms;
+        }
+        if (tmin < best) {
+            best = tmin;
+            bestL = t;
+        }
+        return BQ_OK;
+    };
+    const int max_grid = batch_max_grid(b, 64);
+    for (int wgs = 16; wgs <= max_grid; wgs *= 2) {
+        bq_launch t = L;
+        t.wg_count = wgs;
+        t.ticket_batch = 1;
+        bq_status st = trial(t);
+        if (st != BQ_OK) return st;
+    }
+    {
+        bq_launch t = L;
+        t.wg_count = max_grid;
+        t.ticket_batch = 1;
+        bq_status st = trial(t);
+        if (st != BQ_OK) return st;
+    }
+    const bq_launch cur = bestL;
+    for (int chunk : {256, 4096}) {
+        bq_launch t = cur;
+        t.row_chunk = chunk;
+        bq_status st = trial(t);
+        if (st != BQ_OK) return st;
+    }
+    {
+        bq_launch t = bestL;
+        t.ticket_batch = 2;
+        bq_status st = trial(t);
+        if (st != BQ_OK) return st;
+        t = bestL;
+        t.queue_scale = 1;  // queue capacity pow2(n + m/C + 1) instead of twice that
+        st = trial(t);
+        if (st != BQ_OK) return st;
+    }
+    *h_best = bestL;
+    *h_best_ms = best;
+    return BQ_OK;
+}
+
+}  // extern "C"

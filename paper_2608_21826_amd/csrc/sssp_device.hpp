@@ -1,0 +1,646 @@
+// Device side of the queue-driven Bellman-Ford solver (shared by the
+// single-query and batched launches), for the queue-based Bellman-Ford of
+// Section III.C driven by the Broker Queue of Section III.A.
+//
+// Work item: a vertex u whose distance dropped. A wave dequeues up to 64*b
+// items with one ticket, stages them in LDS with their edge ranges, scans the
+// concatenated CSR rows with all 64 lanes (coalesced reads of cols/w), lowers
+// each target with a 64-bit atomicMin (Alg. 3's relax rule: a source at
+// infinity never relaxes; a target is lowered when source + weight is
+// smaller) and enqueues every target whose distance dropped and that was not
+// already queued.
+//
+// One 64-bit key per vertex carries everything the relax needs, so each
+// step is a single atomic on a single word:
+//
+//      key = d << S | parent << 1 | q        (S = PB + 1, PB = bits for n)
+//
+//  - d: the current distance label (signed); parent: the vertex whose edge
+//    set it (all ones = none); q: 1 while the vertex has an item in the queue.
+//  - relax u->v: atomicMin(key[v], (d_u + w) << S | u << 1 | 1). Signed order
+//    of keys is the order of (d, parent, q). If the minimum took our value,
+//    v's label dropped (or kept its distance with a smaller parent); if the
+//    old q was 0 this lane now owes one enqueue of v; if it was 1 the item
+//    already in the queue will read the new label.
+//  - dequeue of u: atomicAnd(key[u], ~1) clears q and returns the label in
+//    the same atomic, so no relax can slip between the two.
+//  - the final key gives d and, as parent, the smallest-id in-neighbour u
+//    with d(u) + w(u,v) = d(v): every such u relaxes v with its final label
+//    at least once, and the minimum keeps the smallest.
+//
+// High-degree rows are split: a vertex with more than C = 2^chunk_log edges
+// scans only the part of its row inside its first global chunk
+// [jC, (j+1)C) and enqueues the later chunks of its row as items n + j, which
+// other waves take (chunk_owner[j] = u names the vertex).
+//
+// Termination: `pending` counts items enqueued or being processed; a wave
+// leaves when the queue is empty and pending is 0.
+//
+// Negative cycles (Alg. 3 detects them as changes in round n-1; a queue has
+// no rounds): (1) a label below (n-1) * min(0, min w) is impossible without
+// one; (2) once the dequeued work exceeds a few times n, some waves walk the
+// parent pointers (Brent's cycle finding); a closed walk of real edges whose
+// weights sum below zero proves a negative cycle reachable from src.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <limits.h>
+
+#include "bq_device.hpp"
+
+namespace {
+
+using bq::Queue;
+
+constexpr long long KEY_INF = 0x7FFFFFFFFFFFFFFELL;  // d = max, parent = all ones, q = 0
+constexpr int SOLVE_WG = 256;
+constexpr int WAVES_PER_WG = SOLVE_WG / 64;
+constexpr int OUTCAP = 1024;  // LDS push buffer per wave
+#ifndef SSSP_UNROLL
+#define SSSP_UNROLL 8
+#endif
+constexpr int U = SSSP_UNROLL;  // edges per lane per pipelined step
+
+struct SolveArgs {
+    Queue q;
+    const long long* off;
+    const int* col;
+    const int* w;
+    long long* key;          // the caller's dist buffer, used as key array
+    unsigned* chunk_owner;   // [m >> chunk_log + 1]
+    const int* wrange;       // per-block (min w, max w) from k_init
+    int n;
+    int src;
+    long long m;
+    unsigned shift;          // S = PB + 1
+    unsigned chunk_log;
+    unsigned long long limit;     // one wait (ticks of the 100 MHz clock)
+    unsigned long long deadline;  // whole solve
+    unsigned long long* trace;    // optional timeline: 4 words per sample
+    unsigned trace_shift;         // one sample per 2^trace_shift dequeued items
+    unsigned trace_cap;           // samples
+};
+
+__device__ __forceinline__ long long pack_key(long long d, unsigned parent, unsigned shift) {
+    return (long long)(((unsigned long long)d << shift) | ((unsigned long long)parent << 1) | 1ull);
+}
+
+// ---------------------------------------------------------------------------
+// the persistent solver
+// ---------------------------------------------------------------------------
+template <int B>
+struct WaveLds {
+    unsigned item[B];
+    int u[B];
+    long long du[B];
+    long long eb[B];
+    int pre[B + 1];
+    unsigned out[OUTCAP];
+    int fanpre[65];
+};
+
+// Publish `cnt` items from the wave's LDS buffer (Alg. 1 ENQUEUE for all of
+// them at once). pending is raised by `cnt + pending_delta` before any item
+// becomes visible. `release` orders earlier plain stores (the chunk table)
+// before the items. Returns false on abort.
+template <class LDS>
+__device__ bool flush_out(const SolveArgs& a, LDS& L, int cnt, long long pending_delta,
+                          bool release, unsigned long long& spins) {
+    const Queue& q = a.q;
+    const int lane = bq::lane_id();
+    if (cnt == 0) {
+        if (pending_delta != 0 && lane == 0)
+            bq::add_rlx(&q.ctrl->pending.v, (unsigned long long)pending_delta);
+        return true;
+    }
+    unsigned long long base = 0;
+    if (lane == 0) {
+        // pending, ENSURE on count and the tail positions as three atomics in
+        // flight together. In the solver the broker reservation cannot fail:
+        // a vertex holds at most one queue item (its q bit) and chunk items
+        // are bounded, and the capacity is twice that, so count + cnt <= N
+        // always; an overflow would be a bug and stops the solve.
+        bq::add_rlx(&q.ctrl->pending.v, (unsigned long long)((long long)cnt + pending_delta));
+        const long long old = bq::add_rlx(reinterpret_cast<long long*>(&q.ctrl->count.v),
+                                          (long long)cnt);
+        base = bq::add_rlx(&q.ctrl->tail.v, (unsigned long long)cnt);
+        if (old + cnt > (long long)q.N) bq::raise_error(q, bq::ERR_FULL);
+    }
+    base = bq::bcast64(base);
+    if (bq::aborted(q)) return false;
+    if (release) bq::fence_release();
+    for (int c0 = 0; c0 < cnt; c0 += 64) {
+        const int i = c0 + lane;
+        if (!bq::put_slots(q, i < cnt, base + (unsigned long long)i, i < cnt ? L.out[i] : 0u,
+                           a.limit, spins))
+            return false;
+    }
+    return true;
+}
+
+// largest idx in [0, e) with pre[idx] <= t (pre[0] = 0, pre non-decreasing)
+__device__ __forceinline__ int find_item(const int* pre, int e, int t) {
+    int lo = 0, hi = e;  // invariant: pre[lo] <= t < pre[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= t)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ unsigned parent_of(const SolveArgs& a, int x) {
+    const unsigned long long k = (unsigned long long)bq::ld_rlx(&a.key[x]);
+    return (unsigned)((k >> 1) & ((1ull << (a.shift - 1u)) - 1ull));
+}
+
+// minimum weight over edges p -> y (whole wave scans row p); LLONG_MAX if none
+__device__ long long min_edge(const SolveArgs& a, unsigned p, unsigned y) {
+    const long long s = a.off[p], e = a.off[p + 1];
+    long long best = LLONG_MAX;
+    for (long long i = s + bq::lane_id(); i < e; i += 64)
+        if ((unsigned)a.col[i] == y && a.w[i] < best) best = a.w[i];
+    for (int off = 32; off > 0; off >>= 1) {
+        const long long o = __shfl_xor(best, off, 64);
+        best = o < best ? o : best;
+    }
+    return (long long)bq::bcast64((unsigned long long)best);
+}
+
+// Brent's cycle search on the parent pointers from x0; on a cycle, sum the
+// lightest edge of every parent step around it. Wave-uniform.
+__device__ bool walk_finds_negative_cycle(const SolveArgs& a, int x0, unsigned budget) {
+    const unsigned sent = (1u << (a.shift - 1u)) - 1u;
+    unsigned power = 1, lam = 1, steps = 0;
+    unsigned tort = (unsigned)x0;
+    unsigned hare = bq::bcast32(parent_of(a, x0));
+    while (tort != hare) {
+        if (hare == sent) return false;
+        if (power == lam) {
+            tort = hare;
+            power <<= 1;
+            lam = 0;
+        }
+        hare = bq::bcast32(parent_of(a, (int)hare));
+        ++lam;
+        if (++steps > budget) return false;
+        if ((steps & 255u) == 0u && bq::aborted(a.q)) return false;
+    }
+    if (hare == sent) return false;
+    // verify: follow lam parent steps from hare, they must close the walk
+    long long sum = 0;
+    unsigned y = hare;
+    for (unsigned i = 0; i < lam; ++i) {
+        const unsigned p = bq::bcast32(parent_of(a, (int)y));
+        if (p == sent) return false;
+        const long long wmin = min_edge(a, p, y);
+        if (wmin == LLONG_MAX) return false;
+        sum += wmin;
+        y = p;
+    }
+    return y == hare && sum < 0;
+}
+
+// Per-workgroup parking of idle waves: one wave of the workgroup (the
+// poller) watches the global queue state with growing sleeps; the other idle
+// waves sleep on workgroup-local flags. This keeps the number of waves
+// hammering the hot count / pending lines at one per workgroup.
+struct WgShared {
+    int poller;     // wave index of the current poller, -1 if none
+    unsigned wake;  // bumped by the poller when the count turned positive
+    int done;       // pending reached 0: every wave of the workgroup leaves
+};
+
+__device__ __forceinline__ int wg_ld(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ unsigned wg_ld(const unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void wg_st(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Wait for work. Returns 0 when the queue may hold items, 1 when all work is
+// done (pending = 0), -1 on abort / watchdog. Wave-uniform.
+__device__ int idle_wait(const SolveArgs& a, WgShared& S, int wid, unsigned long long& seen_head,
+                         bq::Watch& idle, unsigned long long t_start,
+                         unsigned long long& polls) {
+    const Queue& q = a.q;
+    const int lane = bq::lane_id();
+    while (true) {
+        if (bq::aborted(q)) return -1;
+        if (wg_ld(&S.done)) return 1;
+        int got = 0;
+        if (lane == 0) {
+            int expect = -1;
+            got = __hip_atomic_compare_exchange_strong(&S.poller, &expect, wid, __ATOMIC_RELAXED,
+                                                       __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP)
+                      ? 1
+                      : 0;
+        }
+        if (bq::bcast32((unsigned)got)) {
+            int level = 0;
+            while (true) {
+                ++polls;
+                unsigned long long pend = 0, cnt = 0, hd = 0;
+                if (lane == 0) {
+                    pend = bq::ld_rlx(&q.ctrl->pending.v);
+                    cnt = bq::ld_rlx(&q.ctrl->count.v);
+                    hd = bq::ld_rlx(&q.ctrl->head.v);
+                }
+                pend = bq::bcast64(pend);
+                cnt = bq::bcast64(cnt);
+                hd = bq::bcast64(hd);
+                if (pend == 0ull) {
+                    if (lane == 0) {
+                        wg_st(&S.done, 1);
+                        wg_st(&S.poller, -1);
+                    }
+                    return 1;
+                }
+                if ((long long)cnt > 0) {
+                    if (lane == 0) {
+                        __hip_atomic_fetch_add(&S.wake, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        wg_st(&S.poller, -1);
+                    }
+                    return 0;
+                }
+                if (hd != seen_head) {
+                    seen_head = hd;
+                    idle.arm(a.limit);
+                }
+                const bool late = idle.expired() || bq::now_ticks() - t_start > a.deadline;
+                if (late || bq::aborted(q)) {
+                    if (lane == 0) {
+                        if (late) bq::raise_error(q, bq::ERR_TIMEOUT);
+                        wg_st(&S.poller, -1);
+                    }
+                    return -1;
+                }
+                // one poller per workgroup; keep the pollers together at
+                // about one poll every 0.2 us on the hot lines
+                bq::idle_backoff(level, 8u * gridDim.x);
+                if (level < 20) ++level;
+            }
+        } else {
+            const unsigned w0 = wg_ld(&S.wake);
+            for (unsigned it = 1;; ++it) {
+                __builtin_amdgcn_s_sleep(16);
+                if (wg_ld(&S.done)) return 1;
+                if (wg_ld(&S.wake) != w0) return 0;
+                if (wg_ld(&S.poller) == -1) break;
+                if ((it & 63u) == 0u && bq::aborted(q)) return -1;
+            }
+        }
+    }
+}
+
+// Work counters of one wave.
+struct WaveStats {
+    unsigned long long deq, relax, push, fan, batch, walk, impr, spins, idle, poll;
+};
+
+// Add a wave's counters to a stats block (lane 0; improvements are per lane).
+__device__ inline void flush_stats(bq::Word* stats, WaveStats& st) {
+    const int lane = bq::lane_id();
+    for (int off = 32; off > 0; off >>= 1) st.impr += __shfl_xor(st.impr, off, 64);
+    if (lane == 0) {
+        const unsigned long long v[bq::ST_N] = {st.deq,  st.relax, st.push, st.fan,  st.batch,
+                                                st.walk, st.spins, st.impr, st.idle, st.poll};
+        for (int i = 0; i < bq::ST_N; ++i)
+            if (v[i]) bq::add_rlx(&stats[i].v, v[i]);
+    }
+    st = WaveStats{};
+}
+
+// The persistent solver loop of one wave on one query: dequeue a batch,
+// stage it, scan its edges, publish improved vertices; until the query's
+// pending work is 0 (returns 1) or it is stopped (returns -1). The whole
+// workgroup works on the same query; S must be fresh for it.
+template <int B>
+__device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, int wid,
+                              WaveStats& st) {
+    const Queue& q = a.q;
+    const int lane = bq::lane_id();
+    const unsigned shift = a.shift;
+    const unsigned clog = a.chunk_log;
+    const long long C = 1ll << clog;
+    const unsigned n = (unsigned)a.n;
+
+    // weight range -> packing precondition and the negative-cycle bound
+    long long wmin = INT_MAX, wmax = INT_MIN;
+    {
+        const int parts = (int)bq::ld_rlx(&q.ctrl->aux[0].v);
+        int lo = INT_MAX, hi = INT_MIN;
+        for (int i = lane; i < parts; i += 64) {
+            const int x = a.wrange[2 * i], y = a.wrange[2 * i + 1];
+            lo = x < lo ? x : lo;
+            hi = y > hi ? y : hi;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const int x = __shfl_xor(lo, off, 64), y = __shfl_xor(hi, off, 64);
+            lo = x < lo ? x : lo;
+            hi = y > hi ? y : hi;
+        }
+        wmin = lo;
+        wmax = hi;
+    }
+    const unsigned long long head0 = bq::ld_rlx(&q.ctrl->aux[2].v);
+    long long maxabs = 0;
+    if (a.m > 0) {
+        maxabs = wmax > -wmin ? wmax : -wmin;
+        if (maxabs < 0) maxabs = -maxabs;
+    }
+    // every label of a simple path satisfies |d| <= (n-1) * max|w|; a
+    // candidate is at most one more edge away from a checked label
+    const double lim = (double)(1ull << (62u - shift));
+    if ((double)a.n * (double)maxabs >= lim) {
+        if (threadIdx.x == 0) bq::raise_error(q, bq::ERR_RANGE);
+        return -1;
+    }
+    const long long lbound = (long long)(a.n - 1) * (wmin < 0 ? wmin : 0ll);
+    const unsigned long long suspect_after = 4ull * (unsigned long long)a.n +
+                                             4ull * (unsigned long long)(a.m >> clog) + 4096ull;
+    const unsigned long long walk_stride =
+        (unsigned long long)(a.n / 64 > 256 ? a.n / 64 : 256);
+
+    const unsigned long long t_start = bq::ld_rlx(&q.ctrl->aux[4].v);
+
+    int result = -1;
+    bool had_work = true;  // the first attempt goes straight to the count
+    // an idle wave gives up only if the whole queue stops moving (head
+    // unchanged for `limit`) while work is still pending
+    bq::Watch idle;
+    idle.arm(a.limit);
+    unsigned long long seen_head = 0;
+
+    while (true) {
+        if (bq::aborted(q)) break;
+        if (bq::now_ticks() - t_start > a.deadline) {
+            if (lane == 0) bq::raise_error(q, bq::ERR_TIMEOUT);
+            break;
+        }
+        // ---- DEQUEUE up to B items with one reservation -----------------
+        unsigned e = 0;
+        unsigned long long base = 0;
+        if (lane == 0) {
+            e = bq::reserve_dequeue(q, (unsigned)B, had_work);
+            if (e) base = bq::add_rlx(&q.ctrl->head.v, (unsigned long long)e);
+        }
+        e = bq::bcast32(e);
+        had_work = e > 0;
+        if (e == 0) {
+            ++st.idle;
+            const int r = idle_wait(a, S, wid, seen_head, idle, t_start, st.poll);
+            if (r != 0) {
+                result = r;
+                break;
+            }
+            had_work = true;  // the poller saw a positive count
+            continue;
+        }
+        idle.arm(a.limit);
+        base = bq::bcast64(base);
+        ++st.batch;
+        st.deq += e;
+        bool ok = true;
+        bool any_chunk = false;
+        for (unsigned c0 = 0; c0 < e; c0 += 64) {
+            const unsigned i = c0 + lane;
+            unsigned v = 0;
+            if (!bq::read_slots(q, i < e, base + i, v, a.limit, st.spins)) {
+                ok = false;
+                break;
+            }
+            if (i < e) L.item[i] = v;
+            any_chunk |= __any(i < e && v >= n);
+        }
+        if (!ok) break;
+        // chunk items name their row through chunk_owner, written before
+        // the items were published (release fence on that side)
+        if (any_chunk) bq::fence_acquire();
+        if (a.trace) {
+            const unsigned long long w0 = base - head0, w1 = w0 + e;
+            if ((w0 >> a.trace_shift) != (w1 >> a.trace_shift) && lane == 0) {
+                const unsigned long long idx = w1 >> a.trace_shift;
+                if (idx < a.trace_cap) {
+                    unsigned long long* t = a.trace + 4ull * idx;
+                    t[0] = bq::now_ticks() - t_start;
+                    t[1] = w1;
+                    t[2] = bq::ld_rlx(&q.ctrl->tail.v) - bq::ld_rlx(&q.ctrl->head.v);
+                    t[3] = bq::ld_rlx(&q.ctrl->pending.v);
+                }
+            }
+        }
+
+        // ---- stage the batch: label, edge range, row chunks --------------
+        int carry = 0;
+        int fan_total = 0;
+        for (unsigned c0 = 0; c0 < e; c0 += 64) {
+            const unsigned i = c0 + lane;
+            int cnt = 0, fan = 0;
+            if (i < e) {
+                const unsigned it = L.item[i];
+                int u;
+                long long d, s, t;
+                if (it < n) {
+                    u = (int)it;
+                    const long long old = __hip_atomic_fetch_and(
+                        &a.key[u], ~1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    d = old >> shift;
+                    s = a.off[u];
+                    t = a.off[u + 1];
+                    if (t - s > C) {
+                        const long long js = s >> clog, je = (t - 1) >> clog;
+                        t = (js + 1) << clog;
+                        fan = (int)(je - js);
+                    }
+                } else {
+                    const long long j = (long long)(it - n);
+                    u = (int)bq::ld_rlx(&a.chunk_owner[j]);
+                    d = bq::ld_rlx(&a.key[u]) >> shift;
+                    const long long r0 = a.off[u], r1 = a.off[u + 1];
+                    s = j << clog;
+                    t = (j + 1) << clog;
+                    s = s > r0 ? s : r0;
+                    t = t < r1 ? t : r1;
+                }
+                L.u[i] = u;
+                L.du[i] = d;
+                L.eb[i] = s;
+                cnt = (int)(t - s);
+            }
+            const int incl = bq::wave_incl_scan(cnt);
+            if (i < e) L.pre[i + 1] = carry + incl;
+            carry += __shfl(incl, 63, 64);
+            // fan-out of this 64-item slice: lanes with hubs publish the later
+            // chunks of their rows
+            const int fincl = bq::wave_incl_scan(fan);
+            const int ftot = __shfl(fincl, 63, 64);
+            if (ftot > 0) {
+                L.fanpre[lane + 1] = fincl;
+                if (lane == 0) L.fanpre[0] = 0;
+                __builtin_amdgcn_wave_barrier();
+                for (int t0 = 0; t0 < ftot; t0 += 64) {
+                    const int k = t0 + lane;
+                    // chunk items go through the LDS buffer (at most 64 here)
+                    if (k < ftot) {
+                        int lo = 0, hi = 64;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (L.fanpre[mid] <= k) lo = mid; else hi = mid;
+                        }
+                        const unsigned owner_item = c0 + (unsigned)lo;
+                        const int ou = L.u[owner_item];
+                        const long long js = L.eb[owner_item] >> clog;
+                        const long long j = js + 1 + (k - L.fanpre[lo]);
+                        a.chunk_owner[j] = (unsigned)ou;
+                        L.out[lane] = (unsigned)(n + (unsigned)j);
+                    }
+                    const int cnt_now = (ftot - t0) < 64 ? (ftot - t0) : 64;
+                    __builtin_amdgcn_wave_barrier();
+                    if (!flush_out(a, L, cnt_now, 0, true, st.spins)) {
+                        ok = false;
+                        break;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+                fan_total += ftot;
+                if (!ok) break;
+            }
+        }
+        if (!ok) break;
+        st.fan += (unsigned long long)fan_total;
+        if (lane == 0) L.pre[0] = 0;
+        __builtin_amdgcn_wave_barrier();
+
+        // ---- scan the concatenated edge range ---------------------------
+        // Three-stage software pipeline over groups of 64*U edges: in each
+        // step the wave issues the atomics of group g, the key loads of group
+        // g+1 and the target/weight loads of group g+2, and waits once.
+        // An atomicMin is issued only when the candidate is below the key
+        // loaded one step earlier: keys only decrease, so a candidate that is
+        // not below an earlier value of the key cannot change it, and the
+        // atomic would be a no-op. Most relaxations are such no-ops, and on
+        // high in-degree targets the atomics would otherwise serialize.
+        const int total = carry;
+        st.relax += (unsigned long long)total;
+        int nout = 0;
+        int av[U], aw[U], aidx[U];           // group g+2: target, weight, item
+        int bv[U], bw[U], bidx[U];           // group g+1
+        long long bkey[U];
+        auto fetch = [&](int t0) {
+#pragma unroll
+            for (int r = 0; r < U; ++r) {
+                const int t = t0 + r * 64 + lane;
+                av[r] = -1;
+                aw[r] = 0;
+                aidx[r] = 0;
+                if (t < total) {
+                    const int idx = find_item(L.pre, (int)e, t);
+                    const long long edge = L.eb[idx] + (t - L.pre[idx]);
+                    aidx[r] = idx;
+                    av[r] = a.col[edge];
+                    aw[r] = a.w[edge];
+                }
+            }
+        };
+        // a batch that fits one step skips the key check: there the extra
+        // load would only add a round trip
+        const bool check = total > 64 * U;
+        auto advance = [&]() {  // stage A -> stage B, issuing B's key loads
+#pragma unroll
+            for (int r = 0; r < U; ++r) {
+                bv[r] = av[r];
+                bw[r] = aw[r];
+                bidx[r] = aidx[r];
+                bkey[r] = bv[r] < 0 ? LLONG_MIN
+                                    : (check ? bq::ld_rlx(&a.key[bv[r]]) : LLONG_MAX);
+            }
+        };
+        fetch(0);
+        advance();
+        if (64 * U < total) fetch(64 * U);
+        for (int t0 = 0; t0 < total && ok; t0 += 64 * U) {
+            long long cand[U], cd[U], seen[U];
+            int tv[U];
+            bool valid[U];
+#pragma unroll
+            for (int r = 0; r < U; ++r) {
+                tv[r] = bv[r];
+                valid[r] = tv[r] >= 0;
+                seen[r] = bkey[r];
+                cd[r] = L.du[bidx[r]] + (long long)bw[r];
+                cand[r] = pack_key(cd[r], (unsigned)L.u[bidx[r]], shift);
+            }
+            if (t0 + 64 * U < total) advance();
+            if (t0 + 128 * U < total) fetch(t0 + 128 * U);
+            long long old[U];
+#pragma unroll
+            for (int r = 0; r < U; ++r) {
+                const bool try_it = valid[r] && cand[r] < seen[r];
+                valid[r] = try_it;
+                old[r] = try_it ? __hip_atomic_fetch_min(&a.key[tv[r]], cand[r], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)
+                                : LLONG_MIN;
+            }
+            bool neg = false;
+#pragma unroll
+            for (int r = 0; r < U; ++r) {
+                const bool won = valid[r] && cand[r] < old[r];
+                const bool dropped = won && cd[r] < (old[r] >> shift);
+                st.impr += dropped;
+                neg |= dropped && cd[r] < lbound;
+                const bool push = won && (old[r] & 1ll) == 0;
+                const unsigned long long pm = bq::ballot(push);
+                if (push) L.out[nout + bq::rank_in(pm)] = (unsigned)tv[r];
+                nout += __popcll(pm);
+            }
+            if (__any(neg)) {
+                if (lane == 0) {
+                    bq::st_rlx(&q.ctrl->negcycle.v, 1ull);
+                    bq::st_rlx(&q.ctrl->abort.v, 1ull);
+                }
+                ok = false;
+                break;
+            }
+            if (nout > OUTCAP - 64 * U) {
+                __builtin_amdgcn_wave_barrier();
+                if (!flush_out(a, L, nout, 0, false, st.spins)) {
+                    ok = false;
+                    break;
+                }
+                st.push += (unsigned long long)nout;
+                nout = 0;
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (!ok) break;
+        __builtin_amdgcn_wave_barrier();
+        // publish the rest and retire this batch in one pending update
+        if (!flush_out(a, L, nout, -(long long)e, false, st.spins)) break;
+        st.push += (unsigned long long)nout;
+
+        // ---- negative-cycle search once the work looks unbounded --------
+        const unsigned long long work = base + e - head0;
+        if (work > suspect_after && (base - head0) / walk_stride != work / walk_stride) {
+            ++st.walk;
+            const unsigned budget = (unsigned)(a.n < (1 << 20) ? a.n + 1 : (1 << 20));
+            if (walk_finds_negative_cycle(a, L.u[0], budget)) {
+                if (lane == 0) {
+                    bq::st_rlx(&q.ctrl->negcycle.v, 1ull);
+                    bq::st_rlx(&q.ctrl->abort.v, 1ull);
+                }
+                break;
+            }
+        }
+    }
+
+    return result;
+}
+
+}  // namespace

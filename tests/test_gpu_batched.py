@@ -1,0 +1,178 @@
+"""GPU parity of the batched form (sssp_bf_batched through the C ABI): every
+query in a batch must get exactly the oracle's answer (and so the answer
+sssp_bf gives it alone), whatever else shares the launch."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2608_21826_amd")
+
+DEV = torch.device("cuda:0")
+
+
+def upload(g):
+    return (torch.from_numpy(g.offsets).to(DEV), torch.from_numpy(g.cols).to(DEV),
+            torch.from_numpy(g.w).to(DEV))
+
+
+def make_queries(graphs_srcs):
+    qs, keep = [], []
+    for g, src, t in graphs_srcs:
+        off, col, w = t
+        dist = torch.empty(g.n, dtype=torch.int64, device=DEV)
+        pred = torch.empty(g.n, dtype=torch.int32, device=DEV)
+        qs.append((off, col, w, src, dist, pred))
+        keep.append((g, src))
+    return qs, keep
+
+
+def check_all(qs, keep, neg, method="fifo"):
+    torch.cuda.synchronize()
+    for (off, col, w, src, dist, pred), (g, s), flag in zip(qs, keep, neg):
+        d_ref, p_ref, neg_ref = oracle.sssp(g, s, method=method)
+        assert flag == neg_ref, f"{g.name} src={s}: flag {flag} vs {neg_ref}"
+        if not neg_ref:
+            d = dist.cpu().numpy()
+            p = pred.cpu().numpy()
+            assert np.array_equal(d, d_ref), f"{g.name} src={s}: dist differs"
+            assert np.array_equal(p, p_ref), f"{g.name} src={s}: pred differs"
+
+
+@pytest.fixture(scope="module")
+def batch():
+    b = pkg.SsspBatch(64, 4_000_000, 40_000_000)
+    yield b
+    b.close()
+
+
+def mixed_graphs(seed, k):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(k):
+        kind = i % 4
+        if kind == 0:
+            g = synth.potential_random(int(rng.integers(1, 3000)), int(rng.integers(0, 20000)),
+                                       seed=seed * 100 + i)
+        elif kind == 1:
+            n = int(rng.integers(1, 60))
+            g = synth.random_small(n, int(rng.integers(0, 5 * n + 1)), 0, 20, seed=seed * 100 + i)
+        elif kind == 2:
+            g = synth.erdos_renyi(int(rng.integers(1000, 30000)), 8, seed=seed * 100 + i)
+        else:
+            g = synth.rmat(int(rng.integers(8, 13)), 16, seed=seed * 100 + i)
+        src = int(rng.integers(0, g.n))
+        out.append((g, src, upload(g)))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_mixed_batch_matches_oracle(batch, seed):
+    print(f"[batched] mixed seed={seed}", flush=True)
+    qs, keep = make_queries(mixed_graphs(seed, 24))
+    neg = batch.solve(qs)
+    check_all(qs, keep, neg)
+    st = batch.stats()
+    assert st["relaxations"] > 0
+
+
+@pytest.mark.parametrize("launch", [
+    {"wg_count": 1}, {"wg_count": 3}, {"wg_count": 7, "ticket_batch": 2},
+    {"row_chunk": 256}, {"queue_scale": 1}, {"row_chunk": 64, "wg_count": 16},
+])
+def test_launch_shapes(batch, launch):
+    print(f"[batched] launch {launch}", flush=True)
+    qs, keep = make_queries(mixed_graphs(11, 12))
+    neg = batch.solve(qs, launch=launch)
+    check_all(qs, keep, neg)
+
+
+def test_negative_cycle_in_the_mix(batch):
+    """One query with a planted cycle; it alone is flagged and the others are
+    exact. The next batch (same context) is clean."""
+    items = mixed_graphs(5, 9)
+    gneg = synth.road(40, plant_cycle=True, seed=99)
+    items.insert(4, (gneg, 0, upload(gneg)))
+    qs, keep = make_queries(items)
+    neg = batch.solve(qs)
+    assert neg[4] and sum(neg) == 1
+    check_all(qs, keep, neg)
+    qs2, keep2 = make_queries(mixed_graphs(6, 10))
+    check_all(qs2, keep2, batch.solve(qs2))
+
+
+def test_shared_graph_many_sources(batch):
+    g = synth.rmat(14, 16, seed=4)
+    t = upload(g)
+    srcs = synth.random_sources(g, 32, seed=8)
+    qs, keep = make_queries([(g, int(s), t) for s in srcs])
+    neg = batch.solve(qs)
+    check_all(qs, keep, neg)
+
+
+def test_graph_replay(batch):
+    """The launch sequence as a hipGraph, replayed with eager device work and
+    synchronizations in between; every replay must equal the eager result."""
+    qs, keep = make_queries(mixed_graphs(21, 16))
+    neg0 = batch.solve(qs)
+    ref = [(q[4].clone(), q[5].clone()) for q in qs]
+    for rep in range(4):
+        for q in qs:
+            q[4].fill_(-7)
+            q[5].fill_(-7)
+        junk = torch.randn(1 << 16, device=DEV).sum()
+        torch.cuda.synchronize()
+        neg = batch.solve(qs, graph=True)
+        assert neg == neg0
+        for (d0, p0), q in zip(ref, qs):
+            assert torch.equal(d0, q[4]) and torch.equal(p0, q[5])
+        del junk
+    check_all(qs, keep, neg0)
+
+
+def test_alone_equals_in_mix(batch):
+    items = mixed_graphs(31, 10)
+    qs, keep = make_queries(items)
+    batch.solve(qs)
+    ctx = pkg.SsspContext(200_000, 2_000_000)
+    for (off, col, w, src, dist, pred), (g, s) in zip(qs, keep):
+        d1, p1, n1 = ctx.solve(off, col, w, s)
+        assert torch.equal(d1, dist) and torch.equal(p1, pred)
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# the measured batched workloads
+# ---------------------------------------------------------------------------
+
+def test_er256_full():
+    """256 Erdos-Renyi queries, sizes log-uniform 1k..200k, degree 8."""
+    graphs = synth.er_batch(256)
+    tn = sum(g.n for g in graphs)
+    tm = sum(g.m for g in graphs)
+    print(f"[batched] er256 total n={tn} m={tm}", flush=True)
+    b = pkg.SsspBatch(256, tn, tm)
+    qs, keep = make_queries([(g, g.src, upload(g)) for g in graphs])
+    neg = b.solve(qs, graph=True)
+    print(f"[batched] er256 stats {b.stats()}", flush=True)
+    check_all(qs, keep, neg)
+    b.close()
+
+
+def test_rmat20_64_sources():
+    g = synth.rmat(20)
+    t = upload(g)
+    srcs = synth.random_sources(g, 64, seed=synth.SEED_BASE + 3)
+    b = pkg.SsspBatch(64, 64 * g.n, 64 * g.m)
+    qs, keep = make_queries([(g, int(s), t) for s in srcs])
+    neg = b.solve(qs, graph=True)
+    print(f"[batched] rmat20x64 stats {b.stats()}", flush=True)
+    assert not any(neg)
+    # the oracle on a sample of 12 sources (each ~0.5 s on one core)
+    sample = list(range(0, 64, 6))[:12]
+    check_all([qs[i] for i in sample], [keep[i] for i in sample], [neg[i] for i in sample])
+    b.close()
