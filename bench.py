@@ -126,6 +126,57 @@ def run_probes(pkg, torch, dev):
     return res
 
 
+def reached_edges(torch, dist, deg_t):
+    return int(deg_t[dist != np.iinfo(np.int64).max].sum().item())
+
+
+def batched_leg(pkg, torch, dev, name, queries, graphs, steps, single_launch=None):
+    """One batched launch over all queries vs the same queries one sssp_bf
+    call at a time (each a separate synchronous call). Device time from HIP
+    events in both cases; reached edges summed over the queries."""
+    tn = sum(g.n for g in graphs)
+    tm = sum(g.m for g in graphs)
+    b = pkg.SsspBatch(len(queries), tn, tm)
+    launch, tune_ms = b.autotune(queries)
+    log(f"{name}: batch autotune {launch} {tune_ms:.3f} ms")
+    for _ in range(2):
+        b.solve(queries, launch=launch, graph=True)
+    ms = []
+    for _ in range(steps):
+        b.solve(queries, launch=launch, graph=True)
+        ms.append(b.stats()["ms"])
+    st = b.stats()
+    degs = {}
+    m_reached = 0
+    for (off, col, w, src, dist, pred), g in zip(queries, graphs):
+        key = id(g)
+        if key not in degs:
+            degs[key] = torch.diff(off)
+        m_reached += reached_edges(torch, dist, degs[key])
+    b.close()
+    # one query at a time
+    mx = max(g.n for g in graphs)
+    mm = max(g.m for g in graphs)
+    ctx = pkg.SsspContext(mx, mm)
+    for q in queries[:2]:
+        ctx.solve(q[0], q[1], q[2], q[3], dist=q[4], pred=q[5], launch=single_launch)
+    one_ms = []
+    t0 = time.perf_counter()
+    for q in queries:
+        ctx.solve(q[0], q[1], q[2], q[3], dist=q[4], pred=q[5], launch=single_launch)
+        one_ms.append(ctx.stats()["ms"])
+    one_wall = (time.perf_counter() - t0) * 1e3
+    ctx.close()
+    bms = float(np.median(ms))
+    return {"queries": len(queries), "m_reached": m_reached,
+            "batched_ms": round(bms, 3), "batched_gteps": round(m_reached / bms / 1e6, 3),
+            "one_at_a_time_ms": round(float(np.sum(one_ms)), 3),
+            "one_at_a_time_wall_ms": round(one_wall, 3),
+            "one_at_a_time_gteps": round(m_reached / float(np.sum(one_ms)) / 1e6, 3),
+            "speedup": round(float(np.sum(one_ms)) / bms, 2),
+            "launch": launch, "relaxations": int(st["relaxations"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +192,8 @@ def main():
                     help="library default launch shapes (no autotuning)")
     ap.add_argument("--sssp-only", action="store_true",
                     help="skip the queue leg (for counter passes on the solver kernel)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-one-at-a-time legs")
     ap.add_argument("--probes", action="store_true",
                     help="measure HBM copy and atomic rates (roofline context)")
     args = ap.parse_args()
@@ -280,6 +333,28 @@ def main():
         if probes.get("atomic_min_rand_8MiB_Gops"):
             out["atomic_frac"] = round(
                 (rel / (k_ms.mean() * 1e-3) / 1e9) / probes["atomic_min_rand_8MiB_Gops"], 4)
+    if not args.no_batched and not args.sssp_only:
+        batched = {}
+        srcs = synth.random_sources(g, 64, seed=synth.SEED_BASE + 3)
+        qs = [(off, col, w, int(sv), torch.empty(g.n, dtype=torch.int64, device=dev),
+               torch.empty(g.n, dtype=torch.int32, device=dev)) for sv in srcs]
+        batched["rmat20_x64_sources"] = batched_leg(pkg, torch, dev, "rmat20x64", qs,
+                                                    [g] * len(qs), 5, sssp_launch or None)
+        log(f"batched rmat20x64 {batched['rmat20_x64_sources']}")
+        del qs
+        t0 = time.time()
+        ers = synth.er_batch(256)
+        log(f"er256 generated in {time.time() - t0:.1f}s")
+        qs = []
+        for eg in ers:
+            qs.append((torch.from_numpy(eg.offsets).to(dev), torch.from_numpy(eg.cols).to(dev),
+                       torch.from_numpy(eg.w).to(dev), eg.src,
+                       torch.empty(eg.n, dtype=torch.int64, device=dev),
+                       torch.empty(eg.n, dtype=torch.int32, device=dev)))
+        batched["er256"] = batched_leg(pkg, torch, dev, "er256", qs, ers, 5)
+        log(f"batched er256 {batched['er256']}")
+        del qs, ers
+        out["batched"] = batched
     if not args.no_cpu:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(g, m_reached)
