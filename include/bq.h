@@ -262,6 +262,17 @@ bq_status sssp_batch_destroy(sssp_batch* b);
 bq_status sssp_bf_batched(sssp_batch* b, int32_t count, const sssp_instance* h_inst,
                           int32_t* h_neg_cycle, const bq_launch* launch, void* stream);
 
+/* The two halves of sssp_bf_batched, for callers that overlap work: _start
+ * queues the launch (after work already queued on `stream`) and returns at
+ * once; sssp_batch_finish collects it: with wait = 0 it returns BQ_EBUSY
+ * while the launch runs. h_reached_edges (may be NULL) receives, per query,
+ * the number of edges whose source vertex was reached. A batch object runs
+ * one launch at a time (BQ_EBUSY from _start otherwise). */
+bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instance* h_inst,
+                                const bq_launch* launch, void* stream);
+bq_status sssp_batch_finish(sssp_batch* b, int32_t* h_neg_cycle, int64_t* h_reached_edges,
+                            int32_t wait);
+
 /* Work counters (summed over the batch) and device time of the last call. */
 bq_status sssp_batch_last_stats(const sssp_batch* b, sssp_stats* h_out);
 
@@ -271,6 +282,82 @@ bq_status sssp_batch_last_stats(const sssp_batch* b, sssp_stats* h_out);
 bq_status sssp_batch_autotune(sssp_batch* b, int32_t count, const sssp_instance* h_inst,
                               const bq_launch* base, int32_t reps, bq_launch* h_best,
                               double* h_best_ms, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Served form: resident graphs, admission by memory, continuous batching
+ * ------------------------------------------------------------------------ */
+
+typedef struct bq_server bq_server;
+
+/* One request of a replayed trace. */
+typedef struct {
+    double arrival_us;        /* arrival time, microseconds after the run starts;
+                                 requests must be sorted by it */
+    int32_t graph;            /* resident graph id, or -1: upload the host CSR below */
+    int32_t src;
+    int32_t n;                /* upload only: host CSR (pinned memory keeps the copy */
+    int64_t m;                /*   asynchronous) */
+    const int64_t* h_offsets;
+    const int32_t* h_cols;
+    const int32_t* h_w;
+    int64_t* d_dist;          /* device outputs, may be NULL (then the engine uses */
+    int32_t* d_pred;          /*   its own memory and the result is dropped) */
+} bq_request;
+
+typedef struct {
+    double latency_us;        /* arrival -> completion seen by the engine */
+    double wait_us;           /* arrival -> its launch was queued */
+    double service_us;        /* launch queued -> completion */
+    int64_t reached_edges;    /* edges whose source vertex was reached */
+    int32_t neg_cycle;
+    int32_t status;           /* bq_status of the request (BQ_EINVAL / BQ_EBUSY if rejected) */
+} bq_response;
+
+typedef struct {
+    double wall_ms;
+    uint64_t launches;        /* batched launches started */
+    uint64_t max_inflight;    /* most requests on the device at once */
+    uint64_t max_lanes_busy;  /* most concurrent launches */
+    uint64_t arena_peak_bytes;
+    uint64_t upload_bytes;
+} bq_server_stats;
+
+/* An engine with `lanes` streams (1..16), each able to run one batched
+ * launch of up to max_batch requests whose vertex / edge counts sum to at
+ * most max_batch_n / max_batch_m, and an arena of arena_bytes of device
+ * memory for per-request data (uploaded graphs, engine-owned outputs).
+ * `launch` (may be NULL) is the launch shape of every batched launch. */
+bq_status bq_server_create(int32_t lanes, int32_t max_batch, int64_t max_batch_n,
+                           int64_t max_batch_m, int64_t arena_bytes, const bq_launch* launch,
+                           bq_server** out);
+bq_status bq_server_destroy(bq_server* s);
+
+/* Register a resident graph (device CSR owned by the caller, kept valid
+ * while the server lives); returns its id. */
+bq_status bq_server_add_graph(bq_server* s, int32_t n, int64_t m, const int64_t* d_offsets,
+                              const int32_t* d_cols, const int32_t* d_w, int32_t* graph_id);
+
+/* Replay `count` requests at their arrival times on the calling thread:
+ * arrived requests wait in arrival order; a request is admitted when its
+ * memory (upload + engine outputs) fits the free arena and its sizes fit the
+ * free lane's limits; every free lane starts one batched launch with what is
+ * admitted, so requests arriving while others run are launched on other
+ * lanes and overlap with them. Fills resp[i] per request and *stats
+ * (may be NULL). Returns when every request is done. */
+bq_status bq_server_run(bq_server* s, int32_t count, const bq_request* reqs,
+                        bq_response* resp, bq_server_stats* stats);
+
+/* The engine's first-fit memory arena as a pure host allocator over offsets
+ * (exported so the admission logic can be tested without a device).
+ * Allocation sizes are rounded up to `align` (a power of two); alloc
+ * returns BQ_EBUSY when no free block is large enough; free coalesces. */
+typedef struct bq_arena bq_arena;
+bq_status bq_arena_create(uint64_t size, uint64_t align, bq_arena** out);
+bq_status bq_arena_destroy(bq_arena* a);
+bq_status bq_arena_alloc(bq_arena* a, uint64_t bytes, uint64_t* offset);
+bq_status bq_arena_free(bq_arena* a, uint64_t offset);
+bq_status bq_arena_usage(const bq_arena* a, uint64_t* used, uint64_t* peak,
+                         uint64_t* largest_free);
 
 /* Text for a status code (static storage). */
 const char* bq_strerror(bq_status s);

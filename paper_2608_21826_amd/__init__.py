@@ -28,6 +28,9 @@ EXPORTS = [
     "bq_bench_mixed", "sssp_ctx_create", "sssp_ctx_destroy", "sssp_bf", "sssp_last_stats",
     "sssp_last_trace", "sssp_autotune", "sssp_batch_create", "sssp_batch_destroy",
     "sssp_bf_batched", "sssp_batch_last_stats", "sssp_batch_autotune",
+    "sssp_bf_batched_start", "sssp_batch_finish", "bq_server_create", "bq_server_destroy",
+    "bq_server_add_graph", "bq_server_run", "bq_arena_create", "bq_arena_destroy",
+    "bq_arena_alloc", "bq_arena_free", "bq_arena_usage",
     "bq_strerror", "bq_device_cus", "bq_probe",
 ]
 
@@ -70,6 +73,26 @@ class Instance(ctypes.Structure):
                 ("dist", ctypes.c_void_p), ("pred", ctypes.c_void_p)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("arrival_us", ctypes.c_double), ("graph", ctypes.c_int32),
+                ("src", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("h_offsets", ctypes.c_void_p), ("h_cols", ctypes.c_void_p),
+                ("h_w", ctypes.c_void_p), ("d_dist", ctypes.c_void_p),
+                ("d_pred", ctypes.c_void_p)]
+
+
+class Response(ctypes.Structure):
+    _fields_ = [("latency_us", ctypes.c_double), ("wait_us", ctypes.c_double),
+                ("service_us", ctypes.c_double), ("reached_edges", ctypes.c_int64),
+                ("neg_cycle", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("wall_ms", ctypes.c_double), ("launches", ctypes.c_uint64),
+                ("max_inflight", ctypes.c_uint64), ("max_lanes_busy", ctypes.c_uint64),
+                ("arena_peak_bytes", ctypes.c_uint64), ("upload_bytes", ctypes.c_uint64)]
+
+
 _lib = None
 
 
@@ -110,6 +133,17 @@ def lib(path: str | None = None):
         "sssp_batch_last_stats": ([vp, P(SsspStats)], i32),
         "sssp_batch_autotune": ([vp, i32, P(Instance), P(Launch), i32, P(Launch),
                                  P(ctypes.c_double), vp], i32),
+        "sssp_bf_batched_start": ([vp, i32, P(Instance), P(Launch), vp], i32),
+        "sssp_batch_finish": ([vp, P(i32), P(i64), i32], i32),
+        "bq_server_create": ([i32, i32, i64, i64, i64, P(Launch), P(vp)], i32),
+        "bq_server_destroy": ([vp], i32),
+        "bq_server_add_graph": ([vp, i32, i64, vp, vp, vp, P(i32)], i32),
+        "bq_server_run": ([vp, i32, P(Request), P(Response), P(ServerStats)], i32),
+        "bq_arena_create": ([u64, u64, P(vp)], i32),
+        "bq_arena_destroy": ([vp], i32),
+        "bq_arena_alloc": ([vp, u64, P(u64)], i32),
+        "bq_arena_free": ([vp, u64], i32),
+        "bq_arena_usage": ([vp, P(u64), P(u64), P(u64)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -371,6 +405,114 @@ class SsspBatch:
         s = SsspStats()
         _check(lib().sssp_batch_last_stats(self.handle, ctypes.byref(s)), "sssp_batch_last_stats")
         return s.as_dict()
+
+
+class Server:
+    """bq_server: resident graphs, admission by arena memory, continuous
+    batching over `lanes` streams."""
+
+    def __init__(self, lanes: int, max_batch: int, max_batch_n: int, max_batch_m: int,
+                 arena_bytes: int, launch=None):
+        h = ctypes.c_void_p()
+        _check(lib().bq_server_create(int(lanes), int(max_batch), int(max_batch_n),
+                                      int(max_batch_m), int(arena_bytes), _launch(launch),
+                                      ctypes.byref(h)), "bq_server_create")
+        self.handle = h
+        self._graphs = []
+
+    def close(self):
+        if self.handle:
+            lib().bq_server_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+    def add_graph(self, offsets, cols, w) -> int:
+        import torch
+        n = offsets.numel() - 1
+        _need(offsets, torch.int64, "offsets", n + 1)
+        _need(cols, torch.int32, "cols")
+        _need(w, torch.int32, "w", cols.numel())
+        gid = ctypes.c_int32()
+        _check(lib().bq_server_add_graph(self.handle, n, cols.numel(), _ptr(offsets), _ptr(cols),
+                                         _ptr(w), ctypes.byref(gid)), "bq_server_add_graph")
+        self._graphs.append((offsets, cols, w))
+        return gid.value
+
+    def run(self, requests):
+        """requests: list of dicts with arrival_us, src, and either graph=<id>
+        or upload=(offsets, cols, w) host tensors/arrays (pinned keeps the copy
+        asynchronous); optional dist / pred device tensors. Returns (list of
+        response dicts, stats dict)."""
+        import numpy as np
+        arr = (Request * len(requests))()
+        keep = []
+        for i, r in enumerate(requests):
+            q = Request()
+            q.arrival_us = float(r["arrival_us"])
+            q.src = int(r["src"])
+            if r.get("upload") is not None:
+                off, col, w = r["upload"]
+                keep.append((off, col, w))
+                q.graph = -1
+                q.n = len(off) - 1
+                q.m = len(col)
+                q.h_offsets = _host_ptr(off)
+                q.h_cols = _host_ptr(col)
+                q.h_w = _host_ptr(w)
+            else:
+                q.graph = int(r["graph"])
+            if r.get("dist") is not None:
+                q.d_dist = r["dist"].data_ptr()
+            if r.get("pred") is not None:
+                q.d_pred = r["pred"].data_ptr()
+            arr[i] = q
+        resp = (Response * len(requests))()
+        st = ServerStats()
+        _check(lib().bq_server_run(self.handle, len(requests), arr, resp, ctypes.byref(st)),
+               "bq_server_run")
+        out = [{k: getattr(x, k) for k, _ in x._fields_} for x in resp]
+        return out, {k: getattr(st, k) for k, _ in st._fields_}
+
+
+def _host_ptr(a):
+    try:
+        return a.data_ptr()
+    except AttributeError:
+        return a.ctypes.data
+
+
+class Arena:
+    """The engine's host-side first-fit allocator (no device memory)."""
+
+    def __init__(self, size: int, align: int = 256):
+        h = ctypes.c_void_p()
+        _check(lib().bq_arena_create(int(size), int(align), ctypes.byref(h)), "bq_arena_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().bq_arena_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+    def alloc(self, nbytes: int):
+        off = ctypes.c_uint64()
+        st = lib().bq_arena_alloc(self.handle, int(nbytes), ctypes.byref(off))
+        if st == BQ_EBUSY:
+            return None
+        _check(st, "bq_arena_alloc")
+        return off.value
+
+    def free(self, offset: int):
+        _check(lib().bq_arena_free(self.handle, int(offset)), "bq_arena_free")
+
+    def usage(self):
+        u, p, lf = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().bq_arena_usage(self.handle, ctypes.byref(u), ctypes.byref(p),
+                                    ctypes.byref(lf)), "bq_arena_usage")
+        return u.value, p.value, lf.value
 
 
 def device_cus() -> int:

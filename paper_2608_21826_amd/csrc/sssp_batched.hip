@@ -54,7 +54,8 @@ struct BatchCtl {
 };
 
 __global__ __launch_bounds__(BINIT_WG) void k_binit(const InstDesc* D, const Unit* units,
-                                                    int n_units, int* partials, BatchCtl* bc) {
+                                                    int n_units, int* partials, BatchCtl* bc,
+                                                    unsigned long long* reached) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         bc->cursor.v = 0ull;
         for (int i = 0; i < bq::ST_N; ++i) bc->stats[i].v = 0ull;
@@ -91,6 +92,7 @@ __global__ __launch_bounds__(BINIT_WG) void k_binit(const InstDesc* D, const Uni
             partials[2 * u] = lo;
             partials[2 * u + 1] = hi;
             if (u == d.unit_begin) {
+                reached[d.orig] = 0ull;
                 bq::Ctrl* c = a.q.ctrl;
                 c->pending.v = 1ull;
                 c->abort.v = 0ull;
@@ -157,24 +159,30 @@ __global__ __launch_bounds__(SOLVE_WG) void k_bsolve(const InstDesc* D, int coun
     flush_stats(bc->stats, st);
 }
 
+// Unpack, and count the query's reached edges (out-degrees of reached
+// vertices) for throughput figures.
 __global__ void k_bunpack(const InstDesc* D, const Unit* units, int n_units,
-                          long long* results) {
+                          long long* results, unsigned long long* reached_edges) {
     for (int u = blockIdx.x; u < n_units; u += gridDim.x) {
         const Unit un = units[u];
         const InstDesc& d = D[un.inst];
         const SolveArgs& a = d.a;
         const long long dmax = KEY_INF >> a.shift;
         const unsigned pmask = (1u << (a.shift - 1u)) - 1u;
+        unsigned long long redges = 0;
         for (long long v = un.v0 + threadIdx.x; v < un.v1; v += blockDim.x) {
             const long long k = a.key[v];
             const long long dd = k >> a.shift;
             const bool reached = dd != dmax;
             a.key[v] = reached ? dd : LLONG_MAX;
+            if (reached) redges += (unsigned long long)(a.off[v + 1] - a.off[v]);
             if (d.pred)
                 d.pred[v] = (reached && v != a.src)
                                 ? (int)(((unsigned long long)k >> 1) & pmask)
                                 : -1;
         }
+        for (int off = 32; off > 0; off >>= 1) redges += __shfl_xor(redges, off, 64);
+        if (bq::lane_id() == 0 && redges) bq::add_rlx(&reached_edges[d.orig], redges);
         if (u == d.unit_begin && threadIdx.x == 0) {
             const bq::Ctrl* c = a.q.ctrl;
             results[d.orig] = (long long)(c->negcycle.v & 1ull) |
@@ -210,14 +218,17 @@ struct sssp_batch {
     int* d_claim;
     int* d_partials;
     long long* d_results;
+    unsigned long long* d_reached;
     BatchCtl* d_bc;
     InstDesc* h_desc;
     Unit* h_units;
     int* h_claim;
     long long* h_results;
+    unsigned long long* h_reached;
     BatchCtl* h_bc;
+    int started;  // queries of a started, not yet finished call (0 = none)
     hipStream_t stream;
-    hipEvent_t ev0, ev1, ev_in;
+    hipEvent_t ev0, ev1, ev_in, ev_done;
     std::vector<unsigned long long> layout;
     bool dirty;
     hipGraphExec_t exec;
@@ -234,7 +245,7 @@ bq_status batch_launch_kernels(sssp_batch* b, int count, int n_units, int n_clai
     hipStream_t s = b->stream;
     const int ug = n_units < 2048 ? n_units : 2048;
     hipLaunchKernelGGL(k_binit, dim3(ug), dim3(BINIT_WG), 0, s, b->d_desc, b->d_units, n_units,
-                       b->d_partials, b->d_bc);
+                       b->d_partials, b->d_bc, b->d_reached);
     switch (B) {
         case 64:
             hipLaunchKernelGGL(k_bsolve<64>, dim3(grid), dim3(SOLVE_WG), 0, s, b->d_desc, count,
@@ -250,7 +261,7 @@ bq_status batch_launch_kernels(sssp_batch* b, int count, int n_units, int n_clai
             break;
     }
     hipLaunchKernelGGL(k_bunpack, dim3(ug), dim3(256), 0, s, b->d_desc, b->d_units, n_units,
-                       b->d_results);
+                       b->d_results, b->d_reached);
     BQ_HIP_TRY(hipGetLastError());
     return BQ_OK;
 }
@@ -299,6 +310,7 @@ bq_status sssp_batch_create(int32_t max_instances, int64_t max_total_n, int64_t 
         hipMalloc(&b->d_claim, sizeof(int) * b->max_claim) != hipSuccess ||
         hipMalloc(&b->d_partials, sizeof(int) * 2 * b->max_units) != hipSuccess ||
         hipMalloc(&b->d_results, sizeof(long long) * max_instances) != hipSuccess ||
+        hipMalloc(&b->d_reached, sizeof(unsigned long long) * max_instances) != hipSuccess ||
         hipMalloc(&b->d_bc, sizeof(BatchCtl)) != hipSuccess ||
         hipHostMalloc(&b->h_desc, sizeof(InstDesc) * max_instances, hipHostMallocDefault) !=
             hipSuccess ||
@@ -308,6 +320,8 @@ bq_status sssp_batch_create(int32_t max_instances, int64_t max_total_n, int64_t 
             hipSuccess ||
         hipHostMalloc(&b->h_results, sizeof(long long) * max_instances, hipHostMallocDefault) !=
             hipSuccess ||
+        hipHostMalloc(&b->h_reached, sizeof(unsigned long long) * max_instances,
+                      hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&b->h_bc, sizeof(BatchCtl), hipHostMallocDefault) != hipSuccess) {
         sssp_batch_destroy(b);
         return BQ_ENOMEM;
@@ -316,6 +330,7 @@ bq_status sssp_batch_create(int32_t max_instances, int64_t max_total_n, int64_t 
     BQ_HIP_TRY(hipEventCreate(&b->ev0));
     BQ_HIP_TRY(hipEventCreate(&b->ev1));
     BQ_HIP_TRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+    BQ_HIP_TRY(hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
     b->dirty = true;
     BQ_HIP_TRY(hipMemsetAsync(b->slots, 0, sizeof(unsigned long long) * b->slot_cap, b->stream));
     BQ_HIP_TRY(hipMemsetAsync(b->ctrls, 0, sizeof(bq::Ctrl) * max_instances, b->stream));
@@ -338,16 +353,19 @@ bq_status sssp_batch_destroy(sssp_batch* b) {
     if (b->d_claim) (void)hipFree(b->d_claim);
     if (b->d_partials) (void)hipFree(b->d_partials);
     if (b->d_results) (void)hipFree(b->d_results);
+    if (b->d_reached) (void)hipFree(b->d_reached);
     if (b->d_bc) (void)hipFree(b->d_bc);
     if (b->h_desc) (void)hipHostFree(b->h_desc);
     if (b->h_units) (void)hipHostFree(b->h_units);
     if (b->h_claim) (void)hipHostFree(b->h_claim);
     if (b->h_results) (void)hipHostFree(b->h_results);
+    if (b->h_reached) (void)hipHostFree(b->h_reached);
     if (b->h_bc) (void)hipHostFree(b->h_bc);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_done) (void)hipEventDestroy(b->ev_done);
     delete b;
     return BQ_OK;
 }
@@ -358,9 +376,10 @@ bq_status sssp_batch_last_stats(const sssp_batch* b, sssp_stats* out) {
     return BQ_OK;
 }
 
-bq_status sssp_bf_batched(sssp_batch* b, int32_t count, const sssp_instance* h_inst,
-                          int32_t* h_neg_cycle, const bq_launch* launch, void* stream) {
-    if (!b || !h_inst || !h_neg_cycle || count < 1) return BQ_EINVAL;
+bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instance* h_inst,
+                                const bq_launch* launch, void* stream) {
+    if (!b || !h_inst || count < 1) return BQ_EINVAL;
+    if (b->started) return BQ_EBUSY;
     if (count > b->max_inst) return BQ_EBUSY;
     bqh::Launch L = bqh::resolve(launch, 0);
     if (L.batch != 1 && L.batch != 2 && L.batch != 4) return BQ_EINVAL;
@@ -516,11 +535,32 @@ bq_status sssp_bf_batched(sssp_batch* b, int32_t count, const sssp_instance* h_i
     BQ_HIP_TRY(hipEventRecord(b->ev1, s));
     BQ_HIP_TRY(hipMemcpyAsync(b->h_results, b->d_results, sizeof(long long) * count,
                               hipMemcpyDeviceToHost, s));
+    BQ_HIP_TRY(hipMemcpyAsync(b->h_reached, b->d_reached, sizeof(unsigned long long) * count,
+                              hipMemcpyDeviceToHost, s));
     BQ_HIP_TRY(hipMemcpyAsync(b->h_bc, b->d_bc, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
-    BQ_HIP_TRY(hipStreamSynchronize(s));
+    BQ_HIP_TRY(hipEventRecord(b->ev_done, s));
+    b->started = count;
+    b->last.grid = grid;
+    return BQ_OK;
+}
+
+bq_status sssp_batch_finish(sssp_batch* b, int32_t* h_neg_cycle, int64_t* h_reached_edges,
+                            int32_t wait) {
+    if (!b || !h_neg_cycle) return BQ_EINVAL;
+    const int count = b->started;
+    if (count == 0) return BQ_EINVAL;
+    if (wait) {
+        BQ_HIP_TRY(hipEventSynchronize(b->ev_done));
+    } else {
+        const hipError_t q = hipEventQuery(b->ev_done);
+        if (q == hipErrorNotReady) return BQ_EBUSY;
+        BQ_HIP_TRY(q);
+    }
+    b->started = 0;
     float ms = 0.f;
     BQ_HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
     const BatchCtl* h = b->h_bc;
+    const int grid = b->last.grid;
     b->last = sssp_stats{};
     b->last.dequeued = h->stats[bq::ST_DEQ].v;
     b->last.relaxations = h->stats[bq::ST_RELAX].v;
@@ -539,12 +579,21 @@ bq_status sssp_bf_batched(sssp_batch* b, int32_t count, const sssp_instance* h_i
     for (int i = 0; i < count; ++i) {
         const long long r = b->h_results[i];
         h_neg_cycle[i] = (int32_t)(r & 1);
+        if (h_reached_edges) h_reached_edges[i] = (int64_t)b->h_reached[i];
         const long long err = (r >> 8) & 0xff;
         if (r & ~1ll) b->dirty = true;  // a stopped query leaves its queue non-quiescent
         if (err == bq::ERR_RANGE && ret == BQ_OK) ret = BQ_ERANGE;
         else if (err != 0 && ret == BQ_OK) ret = BQ_ETIMEOUT;
     }
     return ret;
+}
+
+bq_status sssp_bf_batched(sssp_batch* b, int32_t count, const sssp_instance* h_inst,
+                          int32_t* h_neg_cycle, const bq_launch* launch, void* stream) {
+    if (!h_neg_cycle) return BQ_EINVAL;
+    bq_status st = sssp_bf_batched_start(b, count, h_inst, launch, stream);
+    if (st != BQ_OK) return st;
+    return sssp_batch_finish(b, h_neg_cycle, nullptr, 1);
 }
 
 bq_status sssp_batch_autotune(sssp_batch* b, int32_t count, const sssp_instance* h_inst,

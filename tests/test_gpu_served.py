@@ -1,0 +1,152 @@
+"""GPU checks of the served form (bq_server_run through the C ABI): with
+requests arriving while others run, every response equals the oracle (the
+same answer the query gets alone); launches overlap on several lanes;
+admission by memory holds requests back without losing any."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2608_21826_amd")
+
+DEV = torch.device("cuda:0")
+
+
+def dev_csr(g):
+    return (torch.from_numpy(g.offsets).to(DEV), torch.from_numpy(g.cols).to(DEV),
+            torch.from_numpy(g.w).to(DEV))
+
+
+def host_csr(g):
+    return (torch.from_numpy(g.offsets).pin_memory(), torch.from_numpy(g.cols).pin_memory(),
+            torch.from_numpy(g.w).pin_memory())
+
+
+def build_trace(resident, uploads, count, mean_gap_us, seed, outputs=True):
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs, truth = [], []
+    for i in range(count):
+        t += rng.exponential(mean_gap_us)
+        if rng.random() < 0.25 and uploads:
+            g = uploads[int(rng.integers(0, len(uploads)))]
+            src = int(rng.integers(0, g.n))
+            r = {"arrival_us": t, "src": src, "upload": host_csr(g)}
+        else:
+            gid = int(rng.integers(0, len(resident)))
+            g = resident[gid]
+            src = int(rng.integers(0, g.n))
+            r = {"arrival_us": t, "src": src, "graph": gid}
+        if outputs:
+            r["dist"] = torch.empty(g.n, dtype=torch.int64, device=DEV)
+            r["pred"] = torch.empty(g.n, dtype=torch.int32, device=DEV)
+        reqs.append(r)
+        truth.append((g, src))
+    return reqs, truth
+
+
+def make_server(resident, lanes=3, arena=1 << 28, max_batch=16):
+    mn = max(g.n for g in resident) * max_batch
+    mm = max(g.m for g in resident) * max_batch
+    srv = pkg.Server(lanes, max_batch, mn, mm, arena)
+    for g in resident:
+        srv.add_graph(*dev_csr(g))
+    return srv
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    resident = [synth.grid64(), synth.rmat(14, 16, seed=3), synth.erdos_renyi(20000, 8, seed=4)]
+    uploads = [synth.erdos_renyi(5000, 8, seed=5), synth.erdos_renyi(40000, 8, seed=6)]
+    return resident, uploads
+
+
+def check(reqs, truth, resp):
+    torch.cuda.synchronize()
+    for r, (g, src), x in zip(reqs, truth, resp):
+        assert x["status"] == 0
+        d_ref, p_ref, neg = oracle.sssp(g, src, method="fifo")
+        assert bool(x["neg_cycle"]) == neg
+        assert np.array_equal(r["dist"].cpu().numpy(), d_ref)
+        assert np.array_equal(r["pred"].cpu().numpy(), p_ref)
+        deg = np.diff(g.offsets)
+        assert x["reached_edges"] == int(deg[d_ref != oracle.INF].sum())
+        assert x["latency_us"] >= x["wait_us"] >= 0
+
+
+@pytest.mark.parametrize("seed,gap", [(1, 50.0), (2, 300.0)])
+def test_mix_matches_oracle(graphs, seed, gap):
+    resident, uploads = graphs
+    print(f"[served] seed={seed} gap={gap}", flush=True)
+    srv = make_server(resident)
+    reqs, truth = build_trace(resident, uploads, 60, gap, seed)
+    resp, st = srv.run(reqs)
+    print(f"[served] stats {st}", flush=True)
+    check(reqs, truth, resp)
+    assert st["launches"] < len(reqs)      # requests were batched together
+    assert st["max_lanes_busy"] >= 2       # launches overlapped on the device
+    srv.close()
+
+
+def test_alone_equals_in_mix(graphs):
+    resident, uploads = graphs
+    srv = make_server(resident, lanes=1, max_batch=1)
+    reqs, truth = build_trace(resident, uploads, 12, 10.0, 9)
+    resp, st = srv.run(reqs)
+    assert st["launches"] == 12
+    check(reqs, truth, resp)
+    srv.close()
+
+
+def test_admission_by_memory(graphs):
+    """An arena that holds about one uploaded graph at a time: uploads queue
+    up behind each other, nothing is lost, the peak stays within it."""
+    resident, uploads = graphs
+    big = uploads[1]
+    arena = int((big.n + 1) * 8 + big.m * 8 + 4096)
+    srv = make_server(resident, lanes=3, arena=arena)
+    reqs, truth = [], []
+    for i in range(8):
+        g = uploads[i % 2]
+        src = int(i * 37 % g.n)
+        reqs.append({"arrival_us": 10.0 * i, "src": src, "upload": host_csr(g),
+                     "dist": torch.empty(g.n, dtype=torch.int64, device=DEV),
+                     "pred": torch.empty(g.n, dtype=torch.int32, device=DEV)})
+        truth.append((g, src))
+    resp, st = srv.run(reqs)
+    check(reqs, truth, resp)
+    assert st["arena_peak_bytes"] <= arena
+    srv.close()
+
+
+def test_rejections(graphs):
+    resident, uploads = graphs
+    srv = make_server(resident, lanes=2)
+    reqs = [{"arrival_us": 0.0, "src": 0, "graph": 99},
+            {"arrival_us": 1.0, "src": 10**6, "graph": 0},
+            {"arrival_us": 2.0, "src": 0, "graph": 1,
+             "dist": torch.empty(resident[1].n, dtype=torch.int64, device=DEV),
+             "pred": torch.empty(resident[1].n, dtype=torch.int32, device=DEV)}]
+    resp, st = srv.run(reqs)
+    assert resp[0]["status"] == pkg.BQ_EINVAL
+    assert resp[1]["status"] == pkg.BQ_EINVAL
+    assert resp[2]["status"] == 0
+    check(reqs[2:], [(resident[1], 0)], resp[2:])
+    srv.close()
+
+
+def test_engine_outputs_without_caller_buffers(graphs):
+    resident, uploads = graphs
+    srv = make_server(resident, lanes=2)
+    reqs, truth = build_trace(resident, uploads, 30, 40.0, 13, outputs=False)
+    resp, st = srv.run(reqs)
+    for x, (g, src) in zip(resp, truth):
+        assert x["status"] == 0
+        d_ref, _, _ = oracle.sssp(g, src, method="fifo")
+        deg = np.diff(g.offsets)
+        assert x["reached_edges"] == int(deg[d_ref != oracle.INF].sum())
+    srv.close()
