@@ -177,6 +177,78 @@ def batched_leg(pkg, torch, dev, name, queries, graphs, steps, single_launch=Non
             "launch": launch, "relaxations": int(st["relaxations"])}
 
 
+def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0):
+    """Served form (Poisson arrivals over 3 resident graphs + one-off ER
+    uploads): the continuous-batching engine vs the same engine limited to
+    one query per launch and one lane (sequential one-query launches), at
+    1.5x and 0.5x the sequential service rate. p50/p99 latency from arrival
+    to completion; GTEPS = reached edges of all requests / wall time."""
+    import synth
+    rng = np.random.default_rng(synth.SEED_BASE + 4 + seed)
+    road = synth.config_graph("road2048")
+    er = synth.config_graph("er200k")
+    resident = [g_rmat, road, er]
+    dev_csr = [t_rmat] + [(torch.from_numpy(x.offsets).to(dev), torch.from_numpy(x.cols).to(dev),
+                           torch.from_numpy(x.w).to(dev)) for x in (road, er)]
+    up_sizes = np.rint(np.exp(rng.uniform(np.log(1e4), np.log(2e6), size=4))).astype(int)
+    uploads = [synth.erdos_renyi(int(nv), 8, seed=synth.SEED_BASE + 40 + i)
+               for i, nv in enumerate(up_sizes)]
+    pinned = [(torch.from_numpy(x.offsets).pin_memory(), torch.from_numpy(x.cols).pin_memory(),
+               torch.from_numpy(x.w).pin_memory()) for x in uploads]
+    srcs = [synth.random_sources(x, n_req, seed=synth.SEED_BASE + 50 + i)
+            for i, x in enumerate(resident)]
+    mix = []
+    for i in range(n_req):
+        if rng.random() < 0.1:
+            k = int(rng.integers(0, len(uploads)))
+            mix.append(("u", k, int(rng.integers(0, uploads[k].n))))
+        else:
+            k = int(rng.integers(0, 3))
+            mix.append(("g", k, int(srcs[k][i % len(srcs[k])])))
+    max_n = 8 * max(x.n for x in resident + uploads)
+    max_m = 8 * max(x.m for x in resident + uploads)
+
+    def trace(arrivals):
+        out = []
+        for t, (kind, k, src) in zip(arrivals, mix):
+            r = {"arrival_us": float(t), "src": src}
+            if kind == "u":
+                r["upload"] = pinned[k]
+            else:
+                r["graph"] = k
+            out.append(r)
+        return out
+
+    def run(lanes, max_batch, arrivals):
+        srv = pkg.Server(lanes, max_batch, max_n, max_m, 4 << 30)
+        for c in dev_csr:
+            srv.add_graph(*c)
+        srv.run(trace(np.zeros(min(4, n_req))))  # warm-up
+        resp, st = srv.run(trace(arrivals))
+        srv.close()
+        lat = np.array([x["latency_us"] for x in resp]) / 1e3
+        bad = sum(1 for x in resp if x["status"] != 0)
+        edges = sum(x["reached_edges"] for x in resp)
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "mean_ms": round(float(lat.mean()), 3), "wall_ms": round(st["wall_ms"], 1),
+                "gteps": round(edges / (st["wall_ms"] * 1e6), 3), "launches": st["launches"],
+                "max_lanes_busy": st["max_lanes_busy"], "max_inflight": st["max_inflight"],
+                "failed": bad}
+
+    # sequential service time (closed loop: everything queued at t=0)
+    seq0 = run(1, 1, np.zeros(n_req))
+    mean_service_ms = seq0["wall_ms"] / n_req
+    res = {"requests": n_req, "mean_sequential_service_ms": round(mean_service_ms, 3)}
+    for load in (1.5, 0.5):
+        qps = load * 1e3 / mean_service_ms
+        arr = np.cumsum(rng.exponential(1e6 / qps, size=n_req))
+        res[f"qps_{load}x"] = {"qps": round(qps, 2),
+                               "continuous_batching": run(4, 32, arr),
+                               "sequential": run(1, 1, arr)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +266,8 @@ def main():
                     help="skip the queue leg (for counter passes on the solver kernel)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-one-at-a-time legs")
+    ap.add_argument("--served-requests", type=int, default=100,
+                    help="requests per served run (0 skips the served leg)")
     ap.add_argument("--probes", action="store_true",
                     help="measure HBM copy and atomic rates (roofline context)")
     args = ap.parse_args()
@@ -355,6 +429,10 @@ def main():
         log(f"batched er256 {batched['er256']}")
         del qs, ers
         out["batched"] = batched
+    if args.served_requests > 0 and not args.sssp_only:
+        t0 = time.time()
+        out["served"] = served_leg(pkg, torch, dev, g, (off, col, w), args.served_requests)
+        log(f"served leg in {time.time() - t0:.1f}s: {out['served']}")
     if not args.no_cpu:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(g, m_reached)
