@@ -119,7 +119,10 @@ __device__ bool flush_out(const SolveArgs& a, LDS& L, int cnt, long long pending
         // a vertex holds at most one queue item (its q bit) and chunk items
         // are bounded, and the capacity is twice that, so count + cnt <= N
         // always; an overflow would be a bug and stops the solve.
-        bq::add_rlx(&q.ctrl->pending.v, (unsigned long long)((long long)cnt + pending_delta));
+        // a batch that publishes as many items as it retires leaves pending
+        // unchanged: the new items take the place of the retired ones
+        if ((long long)cnt + pending_delta != 0)
+            bq::add_rlx(&q.ctrl->pending.v, (unsigned long long)((long long)cnt + pending_delta));
         const long long old = bq::add_rlx(reinterpret_cast<long long*>(&q.ctrl->count.v),
                                           (long long)cnt);
         base = bq::add_rlx(&q.ctrl->tail.v, (unsigned long long)cnt);
