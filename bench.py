@@ -249,6 +249,47 @@ def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0):
     return res
 
 
+def queue_sweep(pkg, steps=2):
+    """The paper's Section IV queue sweep, on wave64 hardware: both scenarios
+    (Global Mixed, Global EnqDeq), both policies (Broker Queue, BWD),
+    workgroup sizes 64..1024 (the paper's 32..512 threads per block, in whole
+    waves), workgroup counts from the paper's 64/108/216 blocks up to the
+    co-resident grid, and ticket batch b = 1 (one wave op per 64 lanes) and 16.
+    Mixed: 2^20 slots, 2^26 operations. EnqDeq: 2^26 operations on a queue
+    of 2^25 slots, so that every one of the 2^25 enqueues fits and each
+    phase moves real items. Returns rows of Mops/s."""
+    qm = pkg.Queue(QUEUE_CAP)
+    qe = pkg.Queue(QUEUE_OPS // 2)
+    rows = []
+    for scen in ("mixed", "enqdeq"):
+        q = qm if scen == "mixed" else qe
+        for bwd in (False, True):
+            for b in (1, 16):
+                for wgsz in (64, 128, 256, 512, 1024):
+                    for wgs in (64, 108, 216, 512, 0):
+                        L = {"ticket_batch": b, "wg_size": wgsz, "wg_count": wgs,
+                             "flags": pkg.BQ_F_BWD if bwd else 0}
+                        best = None
+                        for _ in range(steps):
+                            if scen == "mixed":
+                                st = q.bench_mixed(QUEUE_OPS, launch=L)[0]
+                                ms, fails = st["ms"], st["enq_full"] + st["deq_empty"]
+                                ok = st["enq_ok"] + st["deq_ok"]
+                            else:
+                                e, d = q.bench_enqdeq(QUEUE_OPS, launch=L)
+                                ms, fails = e["ms"] + d["ms"], e["enq_full"] + d["deq_empty"]
+                                ok = e["enq_ok"] + d["deq_ok"]
+                            if best is None or ms < best[0]:
+                                best = (ms, fails, ok)
+                        rows.append({"scenario": scen, "policy": "BWD" if bwd else "BQ", "b": b,
+                                     "wg_size": wgsz, "wg_count": wgs, "ms": round(best[0], 3),
+                                     "mops": round(QUEUE_OPS / best[0] / 1e3, 1),
+                                     "refused": int(best[1]), "ok": int(best[2])})
+    qm.close()
+    qe.close()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +309,8 @@ def main():
                     help="skip the batched-vs-one-at-a-time legs")
     ap.add_argument("--served-requests", type=int, default=100,
                     help="requests per served run (0 skips the served leg)")
+    ap.add_argument("--queue-sweep", action="store_true",
+                    help="only run the queue scenario / policy / launch-shape sweep")
     ap.add_argument("--probes", action="store_true",
                     help="measure HBM copy and atomic rates (roofline context)")
     args = ap.parse_args()
@@ -280,6 +323,11 @@ def main():
 
     import paper_2608_21826_amd as pkg
     import synth
+
+    if args.queue_sweep:
+        for row in queue_sweep(pkg):
+            print(json.dumps(row), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

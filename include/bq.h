@@ -72,6 +72,10 @@ typedef struct {
 
 #define BQ_F_VALIDATE 1u  /* sssp_bf: check the CSR on the device first */
 #define BQ_F_TRACE 2u     /* sssp_bf: record a timeline (see sssp_last_trace) */
+#define BQ_F_BWD 8u       /* queue operations: the Broker Work Distributor policy
+                             (single-shot broker check: an operation whose
+                             reservation falls short returns Full / Empty at
+                             once instead of re-checking head and tail) */
 #define BQ_F_GRAPH 4u     /* sssp_bf_batched: run the launch sequence as a hipGraph,
                              captured on first use and replayed while the batch
                              keeps its count and shape */
@@ -130,7 +134,9 @@ bq_status bq_destroy(bq_queue* q);
  * zeroed). Needed after BQ_ETIMEOUT. */
 bq_status bq_reset(bq_queue* q, void* stream);
 
-/* ENQUEUE of n values d_vals[0..n) by a launch of wave-aggregated lanes.
+/* ENQUEUE of n values d_vals[0..n) by a launch of wave-aggregated lanes (a
+ * wave moves chunks of 64*b values, b = launch->ticket_batch, 64*b <=
+ * capacity; BQ_F_BWD selects the single-shot broker check).
  * Each value is Successful or Full (Alg. 1); with no concurrent dequeuer the
  * first min(n, capacity - size) positions taken succeed. *d_n_ok (device,
  * uint64, overwritten) receives the number of successes. Which values
@@ -146,6 +152,14 @@ bq_status bq_enqueue(bq_queue* q, const int32_t* d_vals, uint64_t n, uint64_t* d
 bq_status bq_dequeue(bq_queue* q, int32_t* d_out, uint64_t n, uint64_t* d_n_ok,
                      const bq_launch* launch, void* stream);
 
+/* Section IV "Global Enqueue-Dequeue" (EnqDeq): n_ops/2 enqueues (value i
+ * for operation i), then n_ops/2 dequeues, each operation one attempt
+ * (Successful / Full, data / Empty), chunks of 64*b per wave as in
+ * bq_enqueue. The queue is reset to empty first. *h_enq / *h_deq get the
+ * counts and kernel times of the two phases. Synchronous. */
+bq_status bq_bench_enqdeq(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
+                          bq_bench_stats* h_enq, bq_bench_stats* h_deq, void* stream);
+
 /* Host view of the queue counters (synchronizes the stream). */
 bq_status bq_counters(bq_queue* q, void* stream, uint64_t* h_head, uint64_t* h_tail,
                       int64_t* h_count);
@@ -159,7 +173,8 @@ bq_status bq_counters(bq_queue* q, void* stream, uint64_t* h_head, uint64_t* h_t
  * empty first. The value enqueued by operation i is i. If d_enq_log /
  * d_deq_log are not NULL (device, int32[n_ops/2] each) the value written at /
  * read from queue position P is stored at index P, for checking the
- * position rule, conservation and per-producer order: value i belongs to
+ * position rule, conservation and per-producer order (launch->flags may
+ * select BQ_F_BWD): value i belongs to
  * chunk c = i / K of enqueuer wave c mod W (W = *h_enq_waves on return),
  * lane (i mod K) mod 64 of that wave, and is that lane's item number
  * (c / W) * b + (i mod K) / 64. Synchronous. */

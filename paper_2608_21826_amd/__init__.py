@@ -21,11 +21,12 @@ BQ_OK, BQ_EINVAL, BQ_ENOMEM, BQ_EHIP, BQ_ERANGE, BQ_ETIMEOUT, BQ_EBUSY = 0, -1, 
 BQ_F_VALIDATE = 1
 BQ_F_TRACE = 2
 BQ_F_GRAPH = 4
+BQ_F_BWD = 8
 
 # every symbol include/bq.h declares
 EXPORTS = [
     "bq_create", "bq_destroy", "bq_reset", "bq_enqueue", "bq_dequeue", "bq_counters",
-    "bq_bench_mixed", "sssp_ctx_create", "sssp_ctx_destroy", "sssp_bf", "sssp_last_stats",
+    "bq_bench_mixed", "bq_bench_enqdeq", "sssp_ctx_create", "sssp_ctx_destroy", "sssp_bf", "sssp_last_stats",
     "sssp_last_trace", "sssp_autotune", "sssp_batch_create", "sssp_batch_destroy",
     "sssp_bf_batched", "sssp_batch_last_stats", "sssp_batch_autotune",
     "sssp_bf_batched_start", "sssp_batch_finish", "bq_server_create", "bq_server_destroy",
@@ -117,6 +118,7 @@ def lib(path: str | None = None):
         "bq_dequeue": ([vp, vp, u64, vp, P(Launch), vp], i32),
         "bq_counters": ([vp, vp, P(u64), P(u64), P(i64)], i32),
         "bq_bench_mixed": ([vp, u64, P(Launch), vp, vp, P(BenchStats), P(i32), vp], i32),
+        "bq_bench_enqdeq": ([vp, u64, P(Launch), P(BenchStats), P(BenchStats), vp], i32),
         "sssp_ctx_create": ([i32, i64, P(vp)], i32),
         "sssp_ctx_destroy": ([vp], i32),
         "sssp_bf": ([vp, i32, i64, vp, vp, vp, i32, vp, vp, P(i32), P(Launch), vp], i32),
@@ -234,6 +236,14 @@ class Queue:
                                 _stream(stream)), "bq_dequeue")
         k = int(ok.item())
         return out[:k]
+
+    def bench_enqdeq(self, n_ops: int, launch=None, stream=None):
+        """Section IV "Global Enqueue-Dequeue": returns (enqueue stats, dequeue stats)."""
+        e, d = BenchStats(), BenchStats()
+        _check(lib().bq_bench_enqdeq(self.handle, n_ops, _launch(launch), ctypes.byref(e),
+                                     ctypes.byref(d), _stream(stream)), "bq_bench_enqdeq")
+        return ({k: getattr(e, k) for k, _ in e._fields_},
+                {k: getattr(d, k) for k, _ in d._fields_})
 
     def counters(self, stream=None):
         h, t, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int64()

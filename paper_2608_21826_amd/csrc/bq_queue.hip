@@ -36,172 +36,135 @@ __device__ __forceinline__ Queue view(unsigned long long* sl, bq::Ctrl* c, uint3
     return q;
 }
 
-// One wave enqueues the values of its active lanes (Alg. 1 ENQUEUE, all
-// lanes at once). Lanes whose reservation fails retry while the queue is not
-// Full; with `give_up_on_full` they stop (result Full), otherwise they retry
-// after a backoff until they succeed (the benchmark's retry policy).
-// Returns per-lane: 1 success, 0 Full/not active, -1 abort. If `pos_out` is
-// given, the position used is stored there.
-__device__ int wave_enqueue_one(const Queue& q, bool active, uint32_t val, bool give_up_on_full,
-                                unsigned long long limit, unsigned long long& spins,
-                                unsigned long long& fails, unsigned long long* pos_out) {
-    bool want = active;
-    int result = 0;
+// One wave moves one chunk of `cnt` operations (cnt <= 64*b). ENQ: item j
+// enqueues vals[first + j] (or first + j when vals is NULL); !ENQ: item j
+// dequeues into out[] at an index taken from *n_out (compacted, position
+// order within a reservation). Successful items are always a prefix of the
+// chunk, so one wave keeps array order.
+//
+// After a reservation that did not cover the rest of the chunk:
+//  - Broker Queue (Alg. 1 ENQUEUE / DEQUEUE): look at head and tail; if the
+//    queue is not Full (Empty) the shortfall was transient and the wave tries
+//    again at once; if it is, the operations return Full (Empty);
+//  - BWD (bwd = true): the single-shot broker check of the Broker Work
+//    Distributor returns Full (Empty) at once.
+// Operations that returned Full / Empty are retried after a backoff when
+// `retry` is set (the benchmark's policy) and given up otherwise.
+// Returns the number done; *fails counts Full / Empty returns.
+template <bool ENQ>
+__device__ unsigned long long chunk_op(const Queue& q, unsigned long long first,
+                                       unsigned long long cnt, const int32_t* vals, int32_t* out,
+                                       unsigned long long* n_out, int32_t* log,
+                                       bool bwd, bool retry, unsigned long long limit,
+                                       unsigned long long& spins, unsigned long long& fails,
+                                       bool& bad) {
+    const int lane = bq::lane_id();
+    unsigned long long done = 0;
     int level = 0;
     bq::Watch wd;
     wd.arm(limit);
-    while (true) {
-        unsigned long long mask = bq::ballot(want);
-        if (mask == 0ull) break;
-        const uint32_t k = (uint32_t)__popcll(mask);
-        const int rank = bq::rank_in(mask);
+    while (done < cnt) {
         uint32_t e = 0;
-        unsigned long long base = 0;
-        if (bq::lane_id() == 0) {
-            e = bq::reserve_enqueue(q, k);
-            if (e) base = bq::add_rlx(&q.ctrl->tail.v, (unsigned long long)e);
+        unsigned long long base = 0, obase = 0;
+        if (lane == 0) {
+            const uint32_t want = (uint32_t)(cnt - done);
+            e = ENQ ? bq::reserve_enqueue(q, want) : bq::reserve_dequeue(q, want);
+            if (e) {
+                base = bq::add_rlx(ENQ ? &q.ctrl->tail.v : &q.ctrl->head.v, (unsigned long long)e);
+                if (!ENQ && n_out) obase = bq::add_rlx(n_out, (unsigned long long)e);
+            }
         }
         e = bq::bcast32(e);
         base = bq::bcast64(base);
-        const bool mine = want && rank < (int)e;
-        if (e) {
-            const unsigned long long pos = base + (unsigned long long)rank;
-            if (!bq::put_slots(q, mine, pos, val, limit, spins)) return -1;
-            if (mine) {
-                result = 1;
-                want = false;
-                if (pos_out) *pos_out = pos;
+        obase = bq::bcast64(obase);
+        for (uint32_t j0 = 0; j0 < e; j0 += 64) {
+            const uint32_t j = j0 + (uint32_t)lane;
+            const bool act = j < e;
+            const unsigned long long pos = base + j;
+            const unsigned long long item = first + done + j;
+            if (ENQ) {
+                const uint32_t val = act ? (vals ? (uint32_t)vals[item] : (uint32_t)item) : 0u;
+                if (!bq::put_slots(q, act, pos, val, limit, spins)) {
+                    bad = true;
+                    return done;
+                }
+                if (act && log) log[pos] = (int32_t)val;
+            } else {
+                uint32_t val = 0;
+                if (!bq::read_slots(q, act, pos, val, limit, spins)) {
+                    bad = true;
+                    return done;
+                }
+                if (act && out) out[obase + j] = (int32_t)val;
+                if (act && log) log[pos] = (int32_t)val;
             }
         }
-        if (bq::ballot(want) == 0ull) break;
-        // not ensured: Full (return) or a transient state (retry)
-        bool full = false;
-        if (bq::lane_id() == 0) full = bq::looks_full(q);
-        full = bq::bcast32(full) != 0;
-        if (full) {
-            if (want) ++fails;
-            if (give_up_on_full) break;
+        done += e;
+        if (done == cnt) break;
+        bool refused = true;  // BWD: the single-shot check already said Full/Empty
+        if (!bwd) {
+            bool st = false;
+            if (lane == 0) st = ENQ ? bq::looks_full(q) : bq::looks_empty(q);
+            refused = bq::bcast32(st) != 0;
         }
-        if (bq::aborted(q)) return -1;
+        if (refused) {
+            ++fails;
+            if (!retry) break;
+        }
+        if (bq::aborted(q)) {
+            bad = true;
+            break;
+        }
         if (wd.expired()) {
-            if (bq::lane_id() == 0) bq::raise_error(q, bq::ERR_TIMEOUT);
-            return -1;
+            if (lane == 0) bq::raise_error(q, bq::ERR_TIMEOUT);
+            bad = true;
+            break;
         }
-        bq::backoff(level);
-        if (level < 3) ++level;
+        if (refused) {
+            bq::backoff(level);
+            if (level < 3) ++level;
+        }
     }
-    return result;
+    return done;
 }
 
-// Mirror image for DEQUEUE: returns 1 with `val` set, 0 Empty, -1 abort.
-__device__ int wave_dequeue_one(const Queue& q, bool active, uint32_t& val, bool give_up_on_empty,
-                                unsigned long long limit, unsigned long long& spins,
-                                unsigned long long& fails, unsigned long long* pos_out) {
-    bool want = active;
-    int result = 0;
-    int level = 0;
-    bq::Watch wd;
-    wd.arm(limit);
-    while (true) {
-        unsigned long long mask = bq::ballot(want);
-        if (mask == 0ull) break;
-        const uint32_t k = (uint32_t)__popcll(mask);
-        const int rank = bq::rank_in(mask);
-        uint32_t e = 0;
-        unsigned long long base = 0;
-        if (bq::lane_id() == 0) {
-            e = bq::reserve_dequeue(q, k);
-            if (e) base = bq::add_rlx(&q.ctrl->head.v, (unsigned long long)e);
-        }
-        e = bq::bcast32(e);
-        base = bq::bcast64(base);
-        const bool mine = want && rank < (int)e;
-        if (e) {
-            const unsigned long long pos = base + (unsigned long long)rank;
-            uint32_t v = 0;
-            if (!bq::read_slots(q, mine, pos, v, limit, spins)) return -1;
-            if (mine) {
-                val = v;
-                result = 1;
-                want = false;
-                if (pos_out) *pos_out = pos;
-            }
-        }
-        if (bq::ballot(want) == 0ull) break;
-        bool empty = false;
-        if (bq::lane_id() == 0) empty = bq::looks_empty(q);
-        empty = bq::bcast32(empty) != 0;
-        if (empty) {
-            if (want) ++fails;
-            if (give_up_on_empty) break;
-        }
-        if (bq::aborted(q)) return -1;
-        if (wd.expired()) {
-            if (bq::lane_id() == 0) bq::raise_error(q, bq::ERR_TIMEOUT);
-            return -1;
-        }
-        bq::backoff(level);
-        if (level < 3) ++level;
-    }
-    return result;
-}
-
-__global__ void k_bulk_enqueue(unsigned long long* slots, bq::Ctrl* ctrl, uint32_t logN,
-                               const int32_t* vals, unsigned long long n,
-                               unsigned long long* n_ok, unsigned long long limit) {
+// ENQUEUE (ENQ) or DEQUEUE of n operations, grid-stride over chunks of
+// 64*b; every operation makes one attempt (Successful / Full, data / Empty).
+template <bool ENQ>
+__global__ void k_bulk(unsigned long long* slots, bq::Ctrl* ctrl, uint32_t logN,
+                       const int32_t* vals, int32_t* out, unsigned long long n,
+                       unsigned long long* n_ok, unsigned long long* stats,
+                       unsigned long long limit, unsigned b, int bwd) {
     const Queue q = view(slots, ctrl, logN);
     const unsigned long long waves = (unsigned long long)gridDim.x * (blockDim.x >> 6);
     const unsigned long long wave = (unsigned long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const unsigned long long K = 64ull * b;
     unsigned long long ok = 0, spins = 0, fails = 0;
-    for (unsigned long long c = wave; c * 64ull < n; c += waves) {
-        const unsigned long long i = c * 64ull + (unsigned long long)bq::lane_id();
-        const bool active = i < n;
-        const uint32_t v = active ? (uint32_t)vals[i] : 0u;
-        int r = wave_enqueue_one(q, active, v, true, limit, spins, fails, nullptr);
-        if (__any(r < 0)) break;
-        ok += (r == 1);
+    bool bad = false;
+    for (unsigned long long c = wave; c * K < n && !bad; c += waves) {
+        const unsigned long long first = c * K;
+        const unsigned long long cnt = (n - first) < K ? (n - first) : K;
+        ok += chunk_op<ENQ>(q, first, cnt, vals, out, n_ok, nullptr, bwd != 0, false, limit, spins,
+                            fails, bad);
     }
-    // wave reduction of ok
-    for (int off = 32; off > 0; off >>= 1) ok += __shfl_xor(ok, off, 64);
-    if (bq::lane_id() == 0 && ok) bq::add_rlx(n_ok, ok);
-}
-
-__global__ void k_bulk_dequeue(unsigned long long* slots, bq::Ctrl* ctrl, uint32_t logN,
-                               int32_t* out, unsigned long long n, unsigned long long* n_ok,
-                               unsigned long long limit) {
-    const Queue q = view(slots, ctrl, logN);
-    const unsigned long long waves = (unsigned long long)gridDim.x * (blockDim.x >> 6);
-    const unsigned long long wave = (unsigned long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    unsigned long long spins = 0, fails = 0;
-    for (unsigned long long c = wave; c * 64ull < n; c += waves) {
-        const unsigned long long i = c * 64ull + (unsigned long long)bq::lane_id();
-        const bool active = i < n;
-        uint32_t v = 0;
-        int r = wave_dequeue_one(q, active, v, true, limit, spins, fails, nullptr);
-        if (__any(r < 0)) break;
-        // compact the successes of this wave, in position order
-        const unsigned long long m = bq::ballot(r == 1);
-        if (m == 0ull) break;  // queue empty for the whole wave: later waves see it too
-        unsigned long long base = 0;
-        if (bq::lane_id() == 0) base = bq::add_rlx(n_ok, (unsigned long long)__popcll(m));
-        base = bq::bcast64(base);
-        if (r == 1) out[base + (unsigned long long)bq::rank_in(m)] = (int32_t)v;
+    if (bq::lane_id() == 0) {
+        if (ENQ && ok) bq::add_rlx(n_ok, ok);
+        if (stats && fails) bq::add_rlx(&stats[ENQ ? 2 : 3], fails);
+        if (stats && ok) bq::add_rlx(&stats[ENQ ? 0 : 1], ok);
     }
 }
 
 // Section IV "Global Mixed": even workgroups enqueue, odd dequeue. A wave
-// takes chunks of K = 64*b operations (grid-stride over chunks); each chunk
-// is moved with as few broker reservations and head/tail tickets as the
-// queue state allows (one of each when it fits), and an attempt that finds
-// the queue Full / Empty is retried after a backoff until the chunk is done.
-// Enqueue operation i writes value i. stats[0..3] = enq_ok, deq_ok,
-// enq_full, deq_empty.
+// takes chunks of K = 64*b operations (grid-stride over chunks) and moves
+// each with as few broker reservations and head/tail tickets as the queue
+// state allows; operations that return Full / Empty are retried after a
+// backoff until the chunk is done. Enqueue operation i writes value i.
+// stats[0..3] = enq_ok, deq_ok, enq_full, deq_empty.
 __global__ void k_bench_mixed(unsigned long long* slots, bq::Ctrl* ctrl, uint32_t logN,
                               unsigned long long n_half, int32_t* enq_log, int32_t* deq_log,
-                              unsigned long long pos0, unsigned long long* stats,
-                              unsigned long long limit, unsigned b) {
+                              unsigned long long* stats, unsigned long long limit, unsigned b,
+                              int bwd) {
     const Queue q = view(slots, ctrl, logN);
-    const int lane = bq::lane_id();
     const int wpb = blockDim.x >> 6;
     const bool enq = (blockIdx.x & 1u) == 0u;
     const unsigned long long role_blocks = enq ? (gridDim.x + 1u) / 2u : gridDim.x / 2u;
@@ -213,61 +176,12 @@ __global__ void k_bench_mixed(unsigned long long* slots, bq::Ctrl* ctrl, uint32_
     for (unsigned long long c = wave; c * K < n_half && !bad; c += waves) {
         const unsigned long long first = c * K;
         const unsigned long long cnt = (n_half - first) < K ? (n_half - first) : K;
-        unsigned long long done = 0;
-        int level = 0;
-        bq::Watch wd;
-        wd.arm(limit);
-        while (done < cnt) {
-            uint32_t e = 0;
-            unsigned long long base = 0;
-            if (lane == 0) {
-                const uint32_t want = (uint32_t)(cnt - done);
-                e = enq ? bq::reserve_enqueue(q, want) : bq::reserve_dequeue(q, want);
-                if (e) base = bq::add_rlx(enq ? &q.ctrl->tail.v : &q.ctrl->head.v,
-                                          (unsigned long long)e);
-            }
-            e = bq::bcast32(e);
-            base = bq::bcast64(base);
-            for (uint32_t j0 = 0; j0 < e; j0 += 64) {
-                const uint32_t j = j0 + (uint32_t)lane;
-                const bool act = j < e;
-                const unsigned long long pos = base + j;
-                if (enq) {
-                    const uint32_t val = (uint32_t)(first + done + j);
-                    if (!bq::put_slots(q, act, pos, val, limit, spins)) {
-                        bad = true;
-                        break;
-                    }
-                    if (act && enq_log) enq_log[pos - pos0] = (int32_t)val;
-                } else {
-                    uint32_t val = 0;
-                    if (!bq::read_slots(q, act, pos, val, limit, spins)) {
-                        bad = true;
-                        break;
-                    }
-                    if (act && deq_log) deq_log[pos - pos0] = (int32_t)val;
-                }
-            }
-            if (bad) break;
-            done += e;
-            ok += e;
-            if (done < cnt) {
-                ++fails;
-                if (bq::aborted(q)) {
-                    bad = true;
-                    break;
-                }
-                if (wd.expired()) {
-                    if (lane == 0) bq::raise_error(q, bq::ERR_TIMEOUT);
-                    bad = true;
-                    break;
-                }
-                bq::backoff(level);
-                if (level < 3) ++level;
-            }
-        }
+        ok += enq ? chunk_op<true>(q, first, cnt, nullptr, nullptr, nullptr, enq_log, bwd != 0,
+                                   true, limit, spins, fails, bad)
+                  : chunk_op<false>(q, first, cnt, nullptr, nullptr, nullptr, deq_log, bwd != 0,
+                                    true, limit, spins, fails, bad);
     }
-    if (lane == 0) {
+    if (bq::lane_id() == 0) {
         if (ok) bq::add_rlx(&stats[enq ? 0 : 1], ok);
         if (fails) bq::add_rlx(&stats[enq ? 2 : 3], fails);
     }
@@ -405,27 +319,43 @@ static bq_status check_error_and_reset(bq_queue* q, hipStream_t s) {
     return BQ_OK;
 }
 
-static int bulk_grid(const bqh::Launch& L, unsigned long long n) {
-    const unsigned long long waves_needed = (n + 63ull) / 64ull;
-    const unsigned long long wpb = (unsigned long long)(L.wg_size / 64);
-    unsigned long long g = (waves_needed + wpb - 1ull) / wpb;
-    if (g > (unsigned long long)L.wg_count) g = (unsigned long long)L.wg_count;
-    return g < 1ull ? 1 : (int)g;
+static bq_status bulk(bq_queue* q, bool enq, const int32_t* vals, int32_t* out, uint64_t n,
+                      uint64_t* d_n_ok, unsigned long long* d_stats, const bq_launch* launch,
+                      hipStream_t s, bool reset_count) {
+    bqh::Launch L = bqh::resolve(launch, 4 * bqh::device_cus());
+    if (L.wg_size % 64 || L.wg_size > 1024 || L.batch < 1 ||
+        64ull * (unsigned long long)L.batch > q->capacity)
+        return BQ_EINVAL;
+    if (reset_count) BQ_HIP_TRY(hipMemsetAsync(d_n_ok, 0, 8, s));
+    if (n) {
+        const unsigned long long K = 64ull * (unsigned long long)L.batch;
+        const unsigned long long chunks = (n + K - 1) / K;
+        const unsigned long long wpb = (unsigned long long)(L.wg_size / 64);
+        unsigned long long g = (chunks + wpb - 1) / wpb;
+        if (g > (unsigned long long)L.wg_count) g = (unsigned long long)L.wg_count;
+        if (g < 1) g = 1;
+        const int bwd = (L.flags & BQ_F_BWD) ? 1 : 0;
+        if (enq)
+            hipLaunchKernelGGL(k_bulk<true>, dim3((unsigned)g), dim3(L.wg_size), 0, s, q->slots,
+                               q->ctrl, q->logN, vals, (int32_t*)nullptr, (unsigned long long)n,
+                               (unsigned long long*)d_n_ok, d_stats, L.limit,
+                               (unsigned)L.batch, bwd);
+        else
+            hipLaunchKernelGGL(k_bulk<false>, dim3((unsigned)g), dim3(L.wg_size), 0, s, q->slots,
+                               q->ctrl, q->logN, (const int32_t*)nullptr, out,
+                               (unsigned long long)n, (unsigned long long*)d_n_ok, d_stats,
+                               L.limit, (unsigned)L.batch, bwd);
+        BQ_HIP_TRY(hipGetLastError());
+    }
+    return BQ_OK;
 }
 
 bq_status bq_enqueue(bq_queue* q, const int32_t* d_vals, uint64_t n, uint64_t* d_n_ok,
                      const bq_launch* launch, void* stream) {
     if (!q || !d_n_ok || (n && !d_vals)) return BQ_EINVAL;
     hipStream_t s = bqh::as_stream(stream);
-    bqh::Launch L = bqh::resolve(launch, 4 * bqh::device_cus());
-    if (L.wg_size % 64 || L.wg_size > 1024) return BQ_EINVAL;
-    BQ_HIP_TRY(hipMemsetAsync(d_n_ok, 0, 8, s));
-    if (n) {
-        hipLaunchKernelGGL(k_bulk_enqueue, dim3(bulk_grid(L, n)), dim3(L.wg_size), 0, s,
-                           q->slots, q->ctrl, q->logN, d_vals, (unsigned long long)n,
-                           (unsigned long long*)d_n_ok, L.limit);
-        BQ_HIP_TRY(hipGetLastError());
-    }
+    bq_status st = bulk(q, true, d_vals, nullptr, n, d_n_ok, nullptr, launch, s, true);
+    if (st != BQ_OK) return st;
     return check_error_and_reset(q, s);
 }
 
@@ -433,16 +363,42 @@ bq_status bq_dequeue(bq_queue* q, int32_t* d_out, uint64_t n, uint64_t* d_n_ok,
                      const bq_launch* launch, void* stream) {
     if (!q || !d_n_ok || (n && !d_out)) return BQ_EINVAL;
     hipStream_t s = bqh::as_stream(stream);
-    bqh::Launch L = bqh::resolve(launch, 4 * bqh::device_cus());
-    if (L.wg_size % 64 || L.wg_size > 1024) return BQ_EINVAL;
-    BQ_HIP_TRY(hipMemsetAsync(d_n_ok, 0, 8, s));
-    if (n) {
-        hipLaunchKernelGGL(k_bulk_dequeue, dim3(bulk_grid(L, n)), dim3(L.wg_size), 0, s,
-                           q->slots, q->ctrl, q->logN, d_out, (unsigned long long)n,
-                           (unsigned long long*)d_n_ok, L.limit);
-        BQ_HIP_TRY(hipGetLastError());
-    }
+    bq_status st = bulk(q, false, nullptr, d_out, n, d_n_ok, nullptr, launch, s, true);
+    if (st != BQ_OK) return st;
     return check_error_and_reset(q, s);
+}
+
+bq_status bq_bench_enqdeq(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
+                          bq_bench_stats* h_enq, bq_bench_stats* h_deq, void* stream) {
+    if (!q || n_ops < 2 || (n_ops & 1ull) || n_ops / 2 > 0x7fffffffull || !h_enq || !h_deq)
+        return BQ_EINVAL;
+    hipStream_t s = bqh::as_stream(stream);
+    bq_status st = queue_zero(q, s);
+    if (st != BQ_OK) return st;
+    BQ_HIP_TRY(hipMemsetAsync(q->scratch, 0, 128, s));
+    unsigned long long* stats = q->scratch;
+    unsigned long long* cursor = q->scratch + 8;
+    const unsigned long long half = n_ops / 2;
+    hipEvent_t e0 = q->ev0, e1 = q->ev1;
+    hipEvent_t e2;
+    BQ_HIP_TRY(hipEventCreate(&e2));
+    BQ_HIP_TRY(hipEventRecord(e0, s));
+    st = bulk(q, true, nullptr, nullptr, half, (uint64_t*)cursor, stats, launch, s, false);
+    if (st != BQ_OK) return st;
+    BQ_HIP_TRY(hipEventRecord(e1, s));
+    st = bulk(q, false, nullptr, nullptr, half, (uint64_t*)(cursor + 1), stats, launch, s, false);
+    if (st != BQ_OK) return st;
+    BQ_HIP_TRY(hipEventRecord(e2, s));
+    unsigned long long h[4];
+    BQ_HIP_TRY(hipMemcpyAsync(h, stats, sizeof h, hipMemcpyDeviceToHost, s));
+    st = check_error_and_reset(q, s);
+    float ms1 = 0.f, ms2 = 0.f;
+    BQ_HIP_TRY(hipEventElapsedTime(&ms1, e0, e1));
+    BQ_HIP_TRY(hipEventElapsedTime(&ms2, e1, e2));
+    (void)hipEventDestroy(e2);
+    *h_enq = bq_bench_stats{h[0], 0, h[2], 0, ms1};
+    *h_deq = bq_bench_stats{0, h[1], 0, h[3], ms2};
+    return st;
 }
 
 bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
@@ -467,7 +423,6 @@ bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
     if (st != BQ_OK) return st;
     BQ_HIP_TRY(hipMemsetAsync(q->scratch, 0, 64, s));
     unsigned long long n_half = n_ops / 2ull;
-    unsigned long long pos0 = 0ull;
     int32_t* el = d_enq_log;
     int32_t* dl = d_deq_log;
     unsigned long long* stats = q->scratch;
@@ -476,7 +431,8 @@ bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
     uint32_t lg = q->logN;
     unsigned long long lim = L.limit;
     unsigned bb = (unsigned)L.batch;
-    void* args[] = {&sl, &ct, &lg, &n_half, &el, &dl, &pos0, &stats, &lim, &bb};
+    int bwd = (L.flags & BQ_F_BWD) ? 1 : 0;
+    void* args[] = {&sl, &ct, &lg, &n_half, &el, &dl, &stats, &lim, &bb, &bwd};
     BQ_HIP_TRY(hipEventRecord(q->ev0, s));
     BQ_HIP_TRY(hipLaunchCooperativeKernel((const void*)k_bench_mixed, dim3(grid), dim3(L.wg_size),
                                           args, 0, s));

@@ -24,8 +24,14 @@ ONE_WAVE = {"wg_size": 64, "wg_count": 1}
 
 @pytest.mark.parametrize("cap", [64, 128, 1024])
 @pytest.mark.parametrize("seed", range(4))
-def test_one_wave_matches_sequential_fifo(cap, seed):
-    print(f"[queue] one-wave cap={cap} seed={seed}", flush=True)
+@pytest.mark.parametrize("b,flags", [(1, 0), (1, pkg.BQ_F_BWD), (4, 0)])
+def test_one_wave_matches_sequential_fifo(cap, seed, b, flags):
+    """One wave is a sequential client: Broker Queue and BWD alike reduce to
+    the sequential FIFO, also with 64*b operations per ticket."""
+    if 64 * b > cap:
+        pytest.skip("chunk larger than the queue")
+    print(f"[queue] one-wave cap={cap} seed={seed} b={b} flags={flags}", flush=True)
+    ONE = dict(ONE_WAVE, ticket_batch=b, flags=flags)
     rng = np.random.default_rng(seed)
     q = pkg.Queue(cap)
     ops = []          # oracle op list
@@ -36,12 +42,12 @@ def test_one_wave_matches_sequential_fifo(cap, seed):
             k = int(rng.integers(0, 3 * cap // 2))
             vals = np.arange(nxt, nxt + k, dtype=np.int32)
             nxt += k
-            ok = q.enqueue(torch.from_numpy(vals).cuda(), launch=ONE_WAVE) if k else 0
+            ok = q.enqueue(torch.from_numpy(vals).cuda(), launch=ONE) if k else 0
             ops.extend(vals.tolist())
             got_ok.append(("e", k, ok))
         else:
             k = int(rng.integers(0, 3 * cap // 2))
-            out = q.dequeue(k, launch=ONE_WAVE).cpu().numpy() if k else np.zeros(0, np.int32)
+            out = q.dequeue(k, launch=ONE).cpu().numpy() if k else np.zeros(0, np.int32)
             ops.extend([-1] * k)
             got_ok.append(("d", k, out))
     res, out, size = oracle.fifo_run(cap, np.array(ops, dtype=np.int64))
@@ -62,12 +68,15 @@ def test_one_wave_matches_sequential_fifo(cap, seed):
 
 
 @pytest.mark.parametrize("cap", [64, 4096, 1 << 16])
-def test_many_waves_counts_and_conservation(cap):
-    """Success counts follow the FIFO specification exactly; every value that
-    comes out went in (with multiplicity), and everything that went in comes
-    out by the end."""
+@pytest.mark.parametrize("bwd", [False, True])
+def test_many_waves_counts_and_conservation(cap, bwd):
+    """Broker Queue: success counts follow the FIFO specification exactly.
+    BWD (single-shot check, not linearizable) may refuse while room is
+    transiently reserved by others, so it can only fall short. Either way
+    every value that comes out went in once, and all come out by the end."""
     import collections
-    print(f"[queue] many-waves cap={cap}", flush=True)
+    print(f"[queue] many-waves cap={cap} bwd={bwd}", flush=True)
+    L = {"flags": pkg.BQ_F_BWD} if bwd else None
     q = pkg.Queue(cap)
     rng = np.random.default_rng(cap)
     size = 0
@@ -79,20 +88,27 @@ def test_many_waves_counts_and_conservation(cap):
         n = int(rng.integers(1, 3 * cap))
         vals = np.arange(nxt, nxt + n, dtype=np.int32)
         nxt += n
-        ok = q.enqueue(torch.from_numpy(vals).cuda())
-        assert ok == min(n, cap - size)
+        ok = q.enqueue(torch.from_numpy(vals).cuda(), launch=L)
+        if bwd:
+            assert ok <= min(n, cap - size)
+        else:
+            assert ok == min(n, cap - size)
         offered.update(vals.tolist())
         size += ok
         n_in += ok
         h, t, c = q.counters()
         assert t - h == c == size
         k = int(rng.integers(1, 2 * cap))
-        out = q.dequeue(k).cpu().numpy()
-        assert out.size == min(k, size)
+        out = q.dequeue(k, launch=L).cpu().numpy()
+        if bwd:
+            assert out.size <= min(k, size)
+        else:
+            assert out.size == min(k, size)
         size -= out.size
         taken.update(out.tolist())
-    out = q.dequeue(4 * cap).cpu().numpy()
-    taken.update(out.tolist())
+    for _ in range(4):  # BWD may stop early; a few sweeps drain it
+        out = q.dequeue(4 * cap, launch=L).cpu().numpy()
+        taken.update(out.tolist())
     h, t, c = q.counters()
     assert c == 0 and t == h
     assert sum(taken.values()) == n_in
@@ -145,6 +161,32 @@ def test_mixed_small(cap):
 @pytest.mark.parametrize("b", [1, 4, 16])
 def test_mixed_shapes(wgs, wgsize, b):
     _mixed(1024, 1 << 18, {"wg_count": wgs, "wg_size": wgsize, "ticket_batch": b})
+
+
+@pytest.mark.parametrize("b", [1, 8])
+def test_mixed_bwd(b):
+    """The BWD policy under the mixed scenario: every operation still
+    completes (Full/Empty are retried) and the history checks hold."""
+    _mixed(4096, 1 << 20, {"ticket_batch": b, "flags": pkg.BQ_F_BWD})
+
+
+@pytest.mark.parametrize("cap,n_ops", [(1 << 16, 1 << 16), (1 << 12, 1 << 16)])
+@pytest.mark.parametrize("bwd", [False, True])
+def test_enqdeq(cap, n_ops, bwd):
+    """Section IV EnqDeq: all enqueues, then all dequeues, one attempt each."""
+    q = pkg.Queue(cap)
+    L = {"ticket_batch": 4, "flags": pkg.BQ_F_BWD if bwd else 0}
+    e, d = q.bench_enqdeq(n_ops, launch=L)
+    half = n_ops // 2
+    if bwd:
+        assert e["enq_ok"] <= min(half, cap)
+    else:
+        assert e["enq_ok"] == min(half, cap)
+        assert e["enq_full"] >= (1 if half > cap else 0)
+    assert d["deq_ok"] == e["enq_ok"]
+    h, t, c = q.counters()
+    assert c == 0 and t == h
+    q.close()
 
 
 @pytest.mark.parametrize("b", [2, 8])
