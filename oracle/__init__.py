@@ -69,6 +69,8 @@ def load(path: str | None = None):
         lib.oracle_bf_fifo.argtypes = [i32, vp, vp, vp, i32, vp, vp, vp]
         lib.oracle_pred.restype = None
         lib.oracle_pred.argtypes = [i32, vp, vp, vp, i32, vp, vp]
+        lib.oracle_neg_inf.restype = i64
+        lib.oracle_neg_inf.argtypes = [i32, vp, vp, vp, i32, vp, vp]
         lib.oracle_fifo_run.restype = i64
         lib.oracle_fifo_run.argtypes = [i64, i64, vp, vp, vp]
         if path is None:
@@ -123,6 +125,32 @@ def pred(g, dist: np.ndarray, src: int | None = None, lib=None) -> np.ndarray:
     p = np.empty(g.n, dtype=np.int32)
     lib.oracle_pred(g.n, _ptr(off), _ptr(col), _ptr(w), s, _ptr(d), _ptr(p))
     return p
+
+
+NEG_INF = np.iinfo(np.int64).min
+
+
+def neg_inf(g, src: int | None = None, lib=None):
+    """Distances with minus infinity: (dist, pred, neg). dist[v] = NEG_INF
+    for vertices reachable from a negative cycle that src reaches, INF for
+    unreached vertices, the exact distance otherwise; pred = -1 for the
+    minus-infinity vertices, the smallest tight in-neighbour otherwise; neg
+    = some vertex is minus infinity."""
+    lib = lib or load()
+    off, col, w = _csr(g)
+    s = g.src if src is None else int(src)
+    d = np.empty(g.n, dtype=np.int64)
+    mark = np.zeros(g.n, dtype=np.int8)
+    k = lib.oracle_neg_inf(g.n, _ptr(off), _ptr(col), _ptr(w), s, _ptr(d), _ptr(mark))
+    mk = mark.astype(bool)
+    # predecessors of the finite vertices: no marked vertex is an in-neighbour
+    # of an unmarked one, so the marked ones are left out as unreached
+    d_fin = d.copy()
+    d_fin[mk] = INF
+    p = pred(g, d_fin, s, lib)
+    p[mk] = -1
+    d[mk] = NEG_INF
+    return d, p, bool(k > 0)
 
 
 def sssp(g, src: int | None = None, method: str = "rounds", lib=None):

@@ -227,6 +227,73 @@ void oracle_pred(int32_t n, const int64_t *off, const int32_t *col,
 }
 
 /*
+ * Minus-infinity marking (beyond the paper, which only detects): the
+ * distance of v is minus infinity exactly when v is reachable from a negative
+ * cycle that src reaches, because a walk to v can then go round the cycle
+ * as often as wanted. The textbook way to find these vertices with rounds:
+ *  1. n-1 rounds of the round form (oracle_bf_rounds' relax rule, stopping
+ *     early when a round changes nothing). Afterwards every vertex that no
+ *     negative cycle reaches holds its exact distance (a shortest simple
+ *     path has at most n-1 edges) and no label is below the true distance.
+ *  2. Mark v when some edge u->v with d[u] finite still lowers d[v]: then
+ *     d[v] is not exact, so a negative cycle reaches v. Every reachable
+ *     negative cycle has such an edge, since the slacks d[u] + w - d[v]
+ *     round the cycle sum to its (negative) weight.
+ *  3. Spread the marks along edges, round by round, until nothing changes.
+ * Output: mark[v] = 1 for the minus-infinity vertices; d holds the labels
+ * of step 1 (exact for unmarked vertices, INF for unreached ones).
+ * Returns the number of marked vertices.
+ */
+int64_t oracle_neg_inf(int32_t n, const int64_t *off, const int32_t *col,
+                       const int32_t *w, int32_t src, int64_t *d,
+                       int8_t *mark)
+{
+    init_distances(n, src, d);
+    for (int64_t i = 0; i + 1 < n; i++) {
+        int64_t changes = 0;
+        for (int32_t u = 0; u < n; u++) {
+            if (d[u] == ORACLE_INF)
+                continue;
+            for (int64_t e = off[u]; e < off[u + 1]; e++) {
+                int64_t nd = d[u] + (int64_t)w[e];
+                if (nd < d[col[e]]) {
+                    d[col[e]] = nd;
+                    changes++;
+                }
+            }
+        }
+        if (changes == 0)
+            break;
+    }
+    for (int32_t v = 0; v < n; v++)
+        mark[v] = 0;
+    for (int32_t u = 0; u < n; u++) {
+        if (d[u] == ORACLE_INF)
+            continue;
+        for (int64_t e = off[u]; e < off[u + 1]; e++)
+            if (d[u] + (int64_t)w[e] < d[col[e]])
+                mark[col[e]] = 1;
+    }
+    int64_t grew = 1;
+    while (grew) {
+        grew = 0;
+        for (int32_t u = 0; u < n; u++) {
+            if (!mark[u])
+                continue;
+            for (int64_t e = off[u]; e < off[u + 1]; e++)
+                if (!mark[col[e]]) {
+                    mark[col[e]] = 1;
+                    grew = 1;
+                }
+        }
+    }
+    int64_t total = 0;
+    for (int32_t v = 0; v < n; v++)
+        total += mark[v];
+    return total;
+}
+
+/*
  * Sequential bounded FIFO of capacity cap (the sequential specification the
  * concurrent queue must be linearizable to; Section II.B and the queue of
  * Section III.A): enqueue fails (Full) iff it holds cap items, dequeue fails

@@ -22,7 +22,7 @@ import oracle
 import synth
 
 sys.path.insert(0, os.path.dirname(__file__))
-from test_oracle_pins import brute_force  # noqa: E402
+from test_oracle_pins import brute_force, brute_neg_inf  # noqa: E402
 
 SRC = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
 
@@ -43,6 +43,12 @@ MUTANTS = {
     "queue_lifo": ("out[i] = ring[head];\n                head = (head + 1) % cap;",
                    "out[i] = ring[(head + size - 1) % cap];"),
     "queue_capacity": ("if (size == cap) {", "if (size == cap + 1) {"),
+    "neginf_no_spread": ("                if (!mark[col[e]]) {\n                    mark[col[e]] = 1;",
+                         "                if (0) {\n                    mark[col[e]] = 1;"),
+    "neginf_le": ("if (d[u] + (int64_t)w[e] < d[col[e]])\n                mark[col[e]] = 1;",
+                  "if (d[u] + (int64_t)w[e] <= d[col[e]])\n                mark[col[e]] = 1;"),
+    "neginf_short_rounds": ("for (int64_t i = 0; i + 1 < n; i++) {",
+                            "for (int64_t i = 0; i + 2 < n; i++) {"),
 }
 
 
@@ -128,6 +134,23 @@ def _pins_pass(lib) -> bool:
             return False
         g = synth.csr_from_edges(3, [0, 1, 2], [1, 2, 1], [1, 2, -3], source=0)
         if not oracle.bf_fifo(g, None, lib)[1] or not oracle.bf_rounds(g, None, lib)[1]:
+            return False
+        # minus-infinity marking: tiny graphs and a path needing n-1 rounds
+        for seed in range(120):
+            rng = np.random.default_rng(20000 + seed)
+            n = int(rng.integers(1, 8))
+            m = int(rng.integers(0, 3 * n + 1))
+            g = synth.random_small(n, m, -5, 10, seed=21000 + seed)
+            src = int(rng.integers(0, n))
+            d, p, neg = oracle.neg_inf(g, src, lib)
+            if not np.array_equal(d == oracle.NEG_INF, brute_neg_inf(g, src)):
+                return False
+        n = 40
+        ids = np.arange(n)[::-1]
+        w = np.random.default_rng(4).integers(-20, 20, size=n - 1)
+        g = synth.csr_from_edges(n, ids[:-1], ids[1:], w, source=int(ids[0]))
+        d, p, neg = oracle.neg_inf(g, None, lib)
+        if neg or np.any(d == oracle.NEG_INF):
             return False
     except (AssertionError, IndexError, ValueError, OverflowError):
         return False

@@ -82,6 +82,46 @@ def brute_force(g, src):
     return np.array(dist, dtype=np.int64), neg, penult
 
 
+def brute_neg_inf(g, src):
+    """Minus-infinity vertices by enumeration (tiny graphs only): the
+    vertices reachable from a simple cycle of negative weight whose vertices
+    src reaches. Returns a bool array."""
+    n = g.n
+    best = _min_parallel(g)
+    adj = collections.defaultdict(list)
+    for (a, b), c in best.items():
+        adj[a].append((b, c))
+
+    def reach_from(starts):
+        seen = set(starts)
+        todo = list(starts)
+        while todo:
+            u = todo.pop()
+            for v, _ in adj[u]:
+                if v not in seen:
+                    seen.add(v)
+                    todo.append(v)
+        return seen
+
+    reach = reach_from([src])
+    on_neg = set()
+    for s0 in sorted(reach):
+
+        def cyc(u, path, acc):
+            for v, c in adj[u]:
+                if v == s0:
+                    if acc + c < 0:
+                        on_neg.update(path)
+                elif v > s0 and v not in path:
+                    cyc(v, path + [v], acc + c)
+
+        cyc(s0, [s0], 0)
+    out = np.zeros(n, dtype=bool)
+    for v in reach_from(sorted(on_neg)):
+        out[v] = True
+    return out
+
+
 def scipy_dijkstra(g, w=None, src=None):
     """Library Dijkstra on min-deduplicated edges (all weights must be >= 1)."""
     s, d, ww = synth.edges_of(g)
@@ -422,3 +462,72 @@ def test_rmat_medium_rounds_vs_fifo():
     assert np.array_equal(d2, d3)
     assert np.array_equal(d2, johnson_expected(g))
     assert pops >= np.count_nonzero(d2 != INF) - 1
+
+
+# ---------------------------------------------------------------------------
+# minus-infinity marking
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(400))
+def test_neg_inf_brute_tiny(seed):
+    """The marked set is the set reachable from reachable negative simple
+    cycles; every other reached vertex keeps its exact (simple-path) distance
+    and a tight predecessor."""
+    rng = np.random.default_rng(20000 + seed)
+    n = int(rng.integers(1, 8))
+    m = int(rng.integers(0, 3 * n + 1))
+    g = synth.random_small(n, m, -5, 10, seed=21000 + seed)
+    src = int(rng.integers(0, n))
+    d, p, neg = oracle.neg_inf(g, src)
+    mk = brute_neg_inf(g, src)
+    assert np.array_equal(d == oracle.NEG_INF, mk)
+    assert neg == bool(mk.any())
+    assert neg == brute_force(g, src)[1]
+    # vertices no negative cycle reaches: distances of the simple paths that
+    # avoid the marked vertices (a path through one would make them marked)
+    keep = np.nonzero(~mk)[0]
+    sub_s, sub_t, sub_w = synth.edges_of(g)
+    ok = ~mk[sub_s] & ~mk[sub_t]
+    if not mk[src]:
+        sub = synth.csr_from_edges(n, sub_s[ok], sub_t[ok], sub_w[ok], source=src)
+        d_bf, _, _ = brute_force(sub, src)
+        assert np.array_equal(d[keep], d_bf[keep])
+    best = _min_parallel(g)
+    for v in range(n):
+        if mk[v] or d[v] == INF or v == src:
+            assert p[v] == -1
+        else:
+            u = int(p[v])
+            assert (u, v) in best and not mk[u] and d[u] + best[(u, v)] == d[v]
+
+
+def test_neg_inf_no_cycle_is_plain():
+    for seed in range(5):
+        g = synth.potential_random(800, 5000, seed=22000 + seed)
+        d, p, neg = oracle.neg_inf(g)
+        d2, p2, neg2 = oracle.sssp(g, method="fifo")
+        assert not neg and not neg2
+        assert np.array_equal(d, d2) and np.array_equal(p, p2)
+
+
+def test_neg_inf_long_path_then_cycle():
+    """A reversed-id path of 50 vertices needs all n-1 rounds before its end
+    is exact; a negative cycle hangs off the middle and reaches a tail."""
+    n = 60
+    ids = np.arange(50)[::-1]
+    s = list(ids[:-1])
+    t = list(ids[1:])
+    w = list(np.random.default_rng(5).integers(-20, 20, size=49))
+    # cycle 50 -> 51 -> 52 -> 50 of weight -1, entered from path vertex ids[25]
+    s += [int(ids[25]), 50, 51, 52, 52, 53]
+    t += [50, 51, 52, 50, 53, 54]
+    w += [3, 1, 1, -3, 4, 4]
+    g = synth.csr_from_edges(n, s, t, w, source=int(ids[0]))
+    d, p, neg = oracle.neg_inf(g)
+    assert neg
+    exp = np.zeros(50, dtype=np.int64)
+    exp[ids[1:]] = np.cumsum(w[:49])
+    assert np.array_equal(d[:50], exp)
+    assert np.all(d[50:55] == oracle.NEG_INF)
+    assert np.all(d[55:] == INF)
+    assert np.all(p[50:] == -1)
