@@ -16,7 +16,6 @@ Inputs are resident in HBM before the timed region starts.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -26,6 +25,9 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402  (seeded input generators)
+from paper_2608_21826_amd.profsum import kernel_source_hash  # noqa: E402  (no GPU work)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 QUEUE_CAP = 1 << 20
@@ -42,13 +44,6 @@ PMC_FILE = os.path.join(ROOT, "profiles", "sssp_rmat20_pmc.txt")
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("bq_device.hpp", "sssp.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2608_21826_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
 
 
 def read_traffic(per_launch_units):
@@ -183,7 +178,6 @@ def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0):
     one query per launch and one lane (sequential one-query launches), at
     1.5x and 0.5x the sequential service rate. p50/p99 latency from arrival
     to completion; GTEPS = reached edges of all requests / wall time."""
-    import synth
     rng = np.random.default_rng(synth.SEED_BASE + 4 + seed)
     road = synth.config_graph("road2048")
     er = synth.config_graph("er200k")
@@ -290,6 +284,71 @@ def queue_sweep(pkg, steps=2):
     return rows
 
 
+def rounds_leg(pkg, torch, g, off, col, w, ref_dist, m_reached, reps=5):
+    """The paper's own form on the same graph: round-based Bellman-Ford with
+    the queue holding edges (every round relaxes all m edges). Ticket batch
+    b = 4, 16, 64 tried; the distances must equal the queue solver's."""
+    rc = pkg.RoundsContext(g.n, g.m)
+    best = None
+    for b in (4, 16, 64):
+        L = {"ticket_batch": b}
+        for _ in range(reps):
+            d, _, neg = rc.solve(off, col, w, g.src, launch=L, want_pred=True)
+            assert not neg and torch.equal(d, ref_dist), "rounds form: distances differ"
+            st = rc.stats()
+            if best is None or st["ms"] < best[0]["ms"]:
+                best = (st, b)
+    rc.close()
+    st, b = best
+    return {"ms": round(st["ms"], 3), "gteps": round(m_reached / (st["ms"] * 1e-3) / 1e9, 4),
+            "rounds": int(st["rounds"]), "relaxations": int(st["relaxations"]),
+            "changes": int(st["changes"]), "ticket_batch": b, "grid": int(st["grid"]),
+            "relax_per_s_G": round(st["relaxations"] / (st["solve_ms"] * 1e-3) / 1e9, 3)}
+
+
+def bf_sweep(pkg, torch, dev, steps=3):
+    """Queue-driven Bellman-Ford under both broker policies (Broker Queue,
+    BWD), with one queue and with 8 segments, over the paper's block counts
+    64 / 108 / 216, then 512 and the co-resident maximum (8 per CU is more
+    than fits; the library clamps), for ticket batch b = 1 and 4, on RMAT-20
+    and the 2048^2 road graph. Every run's distances must equal the first
+    run's. Returns rows of GTEPS."""
+    rows = []
+    for name in ("rmat20", "road2048"):
+        g = synth.config_graph(name)
+        off = torch.from_numpy(g.offsets).to(dev)
+        col = torch.from_numpy(g.cols).to(dev)
+        w = torch.from_numpy(g.w).to(dev)
+        ctx = pkg.SsspContext(g.n, g.m)
+        ref, _, neg = ctx.solve(off, col, w, g.src, validate=True)
+        assert not neg
+        ref = ref.clone()
+        reached = (ref != np.iinfo(np.int64).max).cpu().numpy()
+        m_reached = int(np.diff(g.offsets)[reached].sum())
+        for bwd, seg in ((False, 1), (True, 1), (False, 8), (True, 8)):
+            for b in (1, 4):
+                for wgs in (64, 108, 216, 512, 8 * pkg.device_cus()):
+                    L = {"ticket_batch": b, "wg_count": wgs, "row_chunk": 256,
+                         "flags": pkg.BQ_F_BWD if bwd else 0, "segments": seg}
+                    best = None
+                    for _ in range(steps):
+                        d, _, neg = ctx.solve(off, col, w, g.src, launch=L)
+                        assert not neg and torch.equal(d, ref), f"{name} {L}: distances differ"
+                        st = ctx.stats()
+                        if best is None or st["ms"] < best["ms"]:
+                            best = st
+                    rows.append({"graph": name, "policy": "BWD" if bwd else "BQ", "b": b,
+                                 "segments": seg,
+                                 "wg_count": int(best["grid"]), "ms": round(best["ms"], 3),
+                                 "gteps": round(m_reached / (best["ms"] * 1e-3) / 1e9, 3),
+                                 "k": round(best["relaxations"] / m_reached, 3),
+                                 "idle_polls": int(best["idle_polls"])})
+                    log(f"bf sweep {rows[-1]}")
+        ctx.close()
+        del off, col, w, ref
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,6 +370,8 @@ def main():
                     help="requests per served run (0 skips the served leg)")
     ap.add_argument("--queue-sweep", action="store_true",
                     help="only run the queue scenario / policy / launch-shape sweep")
+    ap.add_argument("--bf-sweep", action="store_true",
+                    help="only run the solver policy / workgroup-count sweep")
     ap.add_argument("--probes", action="store_true",
                     help="measure HBM copy and atomic rates (roofline context)")
     args = ap.parse_args()
@@ -322,7 +383,6 @@ def main():
     import torch
 
     import paper_2608_21826_amd as pkg
-    import synth
 
     if args.queue_sweep:
         for row in queue_sweep(pkg):
@@ -331,6 +391,11 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.bf_sweep:
+        for row in bf_sweep(pkg, torch, dev):
+            print(json.dumps(row), flush=True)
+        return
+
     t0 = time.time()
     g = synth.rmat(args.scale)
     log(f"graph rmat{args.scale}: n={g.n} m={g.m} src={g.src} ({time.time() - t0:.1f}s)")
@@ -455,6 +520,9 @@ def main():
         if probes.get("atomic_min_rand_8MiB_Gops"):
             out["atomic_frac"] = round(
                 (rel / (k_ms.mean() * 1e-3) / 1e9) / probes["atomic_min_rand_8MiB_Gops"], 4)
+    if not args.sssp_only:
+        out["rounds_form"] = rounds_leg(pkg, torch, g, off, col, w, dist, m_reached)
+        log(f"rounds form {out['rounds_form']}")
     if not args.no_batched and not args.sssp_only:
         batched = {}
         srcs = synth.random_sources(g, 64, seed=synth.SEED_BASE + 3)

@@ -52,6 +52,7 @@ typedef enum {
 typedef struct bq_queue bq_queue;
 typedef struct sssp_ctx sssp_ctx;
 typedef struct sssp_batch sssp_batch;
+typedef struct sssp_rounds_ctx sssp_rounds_ctx;
 
 /* Launch shape. Zero fields mean "library default". */
 typedef struct {
@@ -68,14 +69,30 @@ typedef struct {
     int32_t queue_scale;  /* batched solver: each query's queue holds
                              pow2(queue_scale * (n + m/row_chunk + 1)) slots,
                              1 or 2; 0 = 2 */
+    int32_t segments;     /* sssp_bf: the queue is split into this many
+                             Broker Queues (1..8, one per XCD), workgroup i
+                             publishing to segment i mod segments and taking
+                             from the fullest other segment when its own is
+                             empty; 0 = min(8, workgroups). Forced to 1 with
+                             BQ_F_TRACE. Other calls ignore it. */
 } bq_launch;
 
 #define BQ_F_VALIDATE 1u  /* sssp_bf: check the CSR on the device first */
 #define BQ_F_TRACE 2u     /* sssp_bf: record a timeline (see sssp_last_trace) */
-#define BQ_F_BWD 8u       /* queue operations: the Broker Work Distributor policy
-                             (single-shot broker check: an operation whose
-                             reservation falls short returns Full / Empty at
-                             once instead of re-checking head and tail) */
+#define BQ_F_BWD 8u       /* the Broker Work Distributor policy (Section II):
+                             single-shot broker check. Queue operations: an
+                             operation whose reservation falls short returns
+                             Full / Empty at once instead of re-checking head
+                             and tail. sssp_bf / sssp_bf_batched: each dequeue
+                             takes from the count once, with no look before
+                             or after. Results are the same under both. */
+#define BQ_F_NEGINF 16u   /* sssp_bf, sssp_bf_batched, sssp_bf_rounds: a negative
+                             cycle does not stop the solve; the vertices it
+                             makes unbounded are marked instead: dist[v] =
+                             INT64_MIN for every v reachable from a negative
+                             cycle that src reaches (pred[v] = -1), exact
+                             distances and predecessors for the others, and
+                             the negative-cycle flag is still set. */
 #define BQ_F_GRAPH 4u     /* sssp_bf_batched: run the launch sequence as a hipGraph,
                              captured on first use and replayed while the batch
                              keeps its count and shape */
@@ -103,6 +120,19 @@ typedef struct {
     int32_t grid;          /* workgroups launched */
     int32_t wg_size;
 } sssp_stats;
+
+/* Counters of the last sssp_bf_rounds call. */
+typedef struct {
+    uint64_t rounds;       /* rounds run; the last saw no change unless a
+                              negative cycle or an error ended the solve */
+    uint64_t changes;      /* relaxations that lowered a distance, all rounds */
+    uint64_t relaxations;  /* rounds * m: every round relaxes every edge */
+    uint64_t ticket_spins; /* extra polls of slot words in ticket waits */
+    double ms;             /* device time of the call (HIP events) */
+    double solve_ms;       /* the rounds alone (HIP events) */
+    int32_t grid;          /* workgroups per round kernel */
+    int32_t wg_size;
+} sssp_rounds_stats;
 
 /* One query of sssp_bf_batched: all pointers are device pointers (the
  * layouts and outputs of sssp_bf). */
@@ -199,7 +229,8 @@ bq_status sssp_ctx_destroy(sssp_ctx* ctx);
  * d_pred int32[n] (may be NULL): the smallest-id in-neighbour u with
  * dist[u] + w(u,v) == dist[v], -1 for src and unreachable vertices;
  * *h_neg_cycle: 1 if a negative cycle is reachable from src (then dist and
- * pred are unspecified), else 0. A negative cycle is a result, not an error.
+ * pred are unspecified, unless BQ_F_NEGINF is set: see the flag), else 0.
+ * A negative cycle is a result, not an error.
  *
  * Self-loops and parallel edges are allowed. Requires 1 <= n <= max_n,
  * 0 <= m <= max_m, 0 <= src < n; with BQ_F_VALIDATE the CSR itself is
@@ -214,8 +245,9 @@ bq_status sssp_bf(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
 /* Autotuner: time sssp_bf on this input (d_dist is used as scratch) for
  * workgroup counts 4, 8, 16, ... up to the co-resident maximum (stopping
  * once clearly past the fastest), then ticket batches b = 2, 4 around the
- * fastest count, then row chunks 256 and 4096 at the fastest shape; `reps`
- * runs per candidate (the fastest counts).
+ * fastest count, then row chunks 256 and 4096 at the fastest shape, then
+ * 1, 2 and 4 queue segments against the default; `reps` runs per candidate
+ * (the fastest counts).
  * *h_best gets the fastest launch (other fields copied from `base`, which
  * may be NULL), *h_best_ms its time. Synchronous. */
 bq_status sssp_autotune(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
@@ -232,6 +264,46 @@ bq_status sssp_last_stats(const sssp_ctx* ctx, sssp_stats* h_out);
  * work crosses a multiple of 2^k items (k chosen from n and m), unused
  * samples all ones. Returns the number of samples written, or BQ_EINVAL. */
 int32_t sssp_last_trace(const sssp_ctx* ctx, uint64_t* h_out, int32_t cap_samples);
+
+/* ------------------------------------------------------------------------
+ * Round-based Bellman-Ford over an edge queue (Section III.C's single-GPU
+ * form; Alg. 3 on one processing element)
+ * ------------------------------------------------------------------------ */
+
+/* Workspace for graphs with n <= max_n and m <= max_m: an edge queue of
+ * pow2(max_m) slots (at least 4096; 8 bytes each), the edge-source array
+ * (4 bytes per edge) and the control block. BQ_EINVAL if max_m > 2^31. */
+bq_status sssp_rounds_create(int32_t max_n, int64_t max_m, sssp_rounds_ctx** out);
+bq_status sssp_rounds_destroy(sssp_rounds_ctx* ctx);
+
+/* The paper's own form of the method: the Broker Queue holds edges. Round i
+ * (i = 0 .. n-1) enqueues every edge id and the same launch dequeues and
+ * relaxes them concurrently (d[v] = min(d[v], d[u] + w) when d[u] is
+ * finite, by atomicMin), counting the lowered distances; a round with no
+ * change ends the solve, a change in round n-1 proves a negative cycle.
+ * So the work is (rounds run) * m relaxations, up to n * m.
+ *
+ * Inputs, outputs, conventions and errors are those of sssp_bf (same CSR
+ * arrays, dist INT64_MAX when unreached, pred = smallest-id tight
+ * in-neighbour, -1 for src and unreached; *h_neg_cycle = 1 leaves dist and
+ * pred unspecified unless BQ_F_NEGINF is set), except:
+ *  - BQ_ERANGE when (n+1) * (m+1) * max|w| >= 2^62 (the distances after n
+ *    rounds must not overflow int64);
+ *  - launch: wg_size 64..1024 (power of two), wg_count 0 = 2 per CU
+ *    (clamped to the co-resident maximum), ticket_batch b = 1..64 edge ids
+ *    per lane per queue operation (0 = 16), BQ_F_BWD and BQ_F_VALIDATE as
+ *    for sssp_bf, and BQ_F_NEGINF (minus-infinity marking, see the flag);
+ *    row_chunk, queue_scale and segments are ignored;
+ *  - BQ_ETIMEOUT when one wait exceeds timeout_us or the whole solve
+ *    exceeds 10 x timeout_us (checked between groups of rounds).
+ * Synchronous. */
+bq_status sssp_bf_rounds(sssp_rounds_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
+                         const int32_t* d_cols, const int32_t* d_w, int32_t src,
+                         int64_t* d_dist, int32_t* d_pred, int32_t* h_neg_cycle,
+                         const bq_launch* launch, void* stream);
+
+/* Counters and device time of the last sssp_bf_rounds call on ctx. */
+bq_status sssp_rounds_last_stats(const sssp_rounds_ctx* ctx, sssp_rounds_stats* h_out);
 
 /* ------------------------------------------------------------------------
  * Roofline probes (measurement only)

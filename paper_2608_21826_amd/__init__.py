@@ -6,8 +6,10 @@ shared library is missing the import of a function fails loudly; there is no
 CPU fallback.
 
 Entry points mirror the C names: ``sssp_bf``, ``Queue`` (bq_create,
-bq_enqueue, bq_dequeue, bq_reset, bq_bench_mixed, bq_counters), ``SsspContext``
-(sssp_ctx_create, sssp_last_stats).
+bq_enqueue, bq_dequeue, bq_reset, bq_bench_mixed, bq_bench_enqdeq, bq_counters), ``SsspContext``
+(sssp_ctx_create, sssp_bf, sssp_autotune, sssp_last_stats), ``SsspBatch``
+(the batched form), ``Server`` and ``Arena`` (the served form),
+``RoundsContext`` (sssp_bf_rounds, the round form over an edge queue).
 """
 from __future__ import annotations
 
@@ -22,6 +24,7 @@ BQ_F_VALIDATE = 1
 BQ_F_TRACE = 2
 BQ_F_GRAPH = 4
 BQ_F_BWD = 8
+BQ_F_NEGINF = 16
 
 # every symbol include/bq.h declares
 EXPORTS = [
@@ -33,6 +36,7 @@ EXPORTS = [
     "bq_server_add_graph", "bq_server_run", "bq_arena_create", "bq_arena_destroy",
     "bq_arena_alloc", "bq_arena_free", "bq_arena_usage",
     "bq_strerror", "bq_device_cus", "bq_probe",
+    "sssp_rounds_create", "sssp_rounds_destroy", "sssp_bf_rounds", "sssp_rounds_last_stats",
 ]
 
 
@@ -46,7 +50,7 @@ class Launch(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("wg_count", ctypes.c_int32),
                 ("ticket_batch", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("timeout_us", ctypes.c_uint64), ("row_chunk", ctypes.c_int32),
-                ("queue_scale", ctypes.c_int32)]
+                ("queue_scale", ctypes.c_int32), ("segments", ctypes.c_int32)]
 
 
 class BenchStats(ctypes.Structure):
@@ -63,6 +67,16 @@ class SsspStats(ctypes.Structure):
                 ("ticket_spins", ctypes.c_uint64), ("ms", ctypes.c_double),
                 ("solve_ms", ctypes.c_double), ("grid", ctypes.c_int32),
                 ("wg_size", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RoundsStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_uint64), ("changes", ctypes.c_uint64),
+                ("relaxations", ctypes.c_uint64), ("ticket_spins", ctypes.c_uint64),
+                ("ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("grid", ctypes.c_int32), ("wg_size", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -146,6 +160,10 @@ def lib(path: str | None = None):
         "bq_arena_alloc": ([vp, u64, P(u64)], i32),
         "bq_arena_free": ([vp, u64], i32),
         "bq_arena_usage": ([vp, P(u64), P(u64), P(u64)], i32),
+        "sssp_rounds_create": ([i32, i64, P(vp)], i32),
+        "sssp_rounds_destroy": ([vp], i32),
+        "sssp_bf_rounds": ([vp, i32, i64, vp, vp, vp, i32, vp, vp, P(i32), P(Launch), vp], i32),
+        "sssp_rounds_last_stats": ([vp, P(RoundsStats)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -272,6 +290,28 @@ class Queue:
 # ---------------------------------------------------------------------------
 # SSSP
 # ---------------------------------------------------------------------------
+def _solve_args(offsets, cols, w, dist, pred, want_pred, launch, flags):
+    import torch
+    n = offsets.numel() - 1
+    m = cols.numel()
+    _need(offsets, torch.int64, "offsets", n + 1)
+    _need(cols, torch.int32, "cols")
+    _need(w, torch.int32, "w", m)
+    dev = offsets.device
+    if dist is None:
+        dist = torch.empty(n, dtype=torch.int64, device=dev)
+    _need(dist, torch.int64, "dist", n)
+    if want_pred and pred is None:
+        pred = torch.empty(n, dtype=torch.int32, device=dev)
+    if pred is not None:
+        _need(pred, torch.int32, "pred", n)
+    L = launch
+    if flags:
+        L = Launch(**(launch or {})) if not isinstance(launch, Launch) else launch
+        L.flags |= flags
+    return n, m, dist, pred, L
+
+
 class SsspContext:
     """Workspace for graphs up to max_n vertices and max_m edges."""
 
@@ -289,26 +329,14 @@ class SsspContext:
     __del__ = close
 
     def solve(self, offsets, cols, w, src: int, dist=None, pred=None, want_pred=True,
-              launch=None, validate=False, trace=False, stream=None):
-        """sssp_bf on device tensors; returns (dist int64, pred int32 or None, neg bool)."""
-        import torch
-        n = offsets.numel() - 1
-        m = cols.numel()
-        _need(offsets, torch.int64, "offsets", n + 1)
-        _need(cols, torch.int32, "cols")
-        _need(w, torch.int32, "w", m)
-        dev = offsets.device
-        if dist is None:
-            dist = torch.empty(n, dtype=torch.int64, device=dev)
-        _need(dist, torch.int64, "dist", n)
-        if want_pred and pred is None:
-            pred = torch.empty(n, dtype=torch.int32, device=dev)
-        if pred is not None:
-            _need(pred, torch.int32, "pred", n)
-        L = launch
-        if validate or trace:
-            L = Launch(**(launch or {})) if not isinstance(launch, Launch) else launch
-            L.flags |= (BQ_F_VALIDATE if validate else 0) | (BQ_F_TRACE if trace else 0)
+              launch=None, validate=False, trace=False, neg_inf=False, stream=None):
+        """sssp_bf on device tensors; returns (dist int64, pred int32 or None, neg bool).
+        With neg_inf, a negative cycle leaves dist = INT64_MIN on the vertices
+        it reaches and exact results elsewhere."""
+        n, m, dist, pred, L = _solve_args(offsets, cols, w, dist, pred, want_pred, launch,
+                                          (BQ_F_VALIDATE if validate else 0) |
+                                          (BQ_F_TRACE if trace else 0) |
+                                          (BQ_F_NEGINF if neg_inf else 0))
         neg = ctypes.c_int32(0)
         _check(lib().sssp_bf(self.handle, n, m, _ptr(offsets), _ptr(cols), _ptr(w), int(src),
                              _ptr(dist), _ptr(pred), ctypes.byref(neg), _launch(L),
@@ -536,3 +564,45 @@ def probe(kind: int, a, b=None, size: int = 0, ops_per_lane: int = 0, grid: int 
     _check(lib().bq_probe(int(kind), _ptr(a), _ptr(b), int(size), int(ops_per_lane), int(grid),
                           int(block), ctypes.byref(ms), _stream(stream)), "bq_probe")
     return ms.value
+
+
+# ---------------------------------------------------------------------------
+# round-based Bellman-Ford over an edge queue
+# ---------------------------------------------------------------------------
+class RoundsContext:
+    """sssp_rounds_create / sssp_bf_rounds: the paper's round form with the
+    queue holding edges. Workspace for up to max_n vertices, max_m edges."""
+
+    def __init__(self, max_n: int, max_m: int):
+        h = ctypes.c_void_p()
+        _check(lib().sssp_rounds_create(int(max_n), int(max_m), ctypes.byref(h)),
+               "sssp_rounds_create")
+        self.handle = h
+        self.max_n, self.max_m = int(max_n), int(max_m)
+
+    def close(self):
+        if self.handle:
+            lib().sssp_rounds_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+    def solve(self, offsets, cols, w, src: int, dist=None, pred=None, want_pred=True,
+              launch=None, validate=False, neg_inf=False, stream=None):
+        """sssp_bf_rounds on device tensors; returns (dist, pred or None, neg).
+        With neg_inf, a negative cycle leaves dist = INT64_MIN on the vertices
+        it reaches and exact results elsewhere."""
+        n, m, dist, pred, L = _solve_args(offsets, cols, w, dist, pred, want_pred, launch,
+                                          (BQ_F_VALIDATE if validate else 0) |
+                                          (BQ_F_NEGINF if neg_inf else 0))
+        neg = ctypes.c_int32(0)
+        _check(lib().sssp_bf_rounds(self.handle, n, m, _ptr(offsets), _ptr(cols), _ptr(w),
+                                    int(src), _ptr(dist), _ptr(pred), ctypes.byref(neg),
+                                    _launch(L), _stream(stream)), "sssp_bf_rounds")
+        return dist, pred, bool(neg.value)
+
+    def stats(self) -> dict:
+        s = RoundsStats()
+        _check(lib().sssp_rounds_last_stats(self.handle, ctypes.byref(s)),
+               "sssp_rounds_last_stats")
+        return s.as_dict()

@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["bq_queue.hip", "sssp.hip", "sssp_batched.hip", "server.hip", "probes.hip"]
+SOURCES = ["bq_queue.hip", "sssp.hip", "sssp_rounds.hip", "sssp_batched.hip", "server.hip",
+           "probes.hip"]
 LIB = os.path.join(HERE, "libbqsssp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

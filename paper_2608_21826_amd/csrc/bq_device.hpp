@@ -213,6 +213,25 @@ __device__ __forceinline__ uint32_t reserve_dequeue(const Queue& q, uint32_t k,
     return e;
 }
 
+// Alg. 1 ENSURE_DEQUEUE as the solver runs it, under the two broker
+// policies (leader lane only).
+//  - Broker Queue: look at the count, take what it shows and, when a lost
+//    race leaves the take empty while the count still shows items, look
+//    again (the continuous re-validation; bounded here because the caller's
+//    idle loop polls again anyway).
+//  - BWD: a single take of k with no look before or after it: the count is
+//    a snapshot, and a take that finds it short reports Empty.
+__device__ __forceinline__ uint32_t ensure_dequeue(const Queue& q, uint32_t k, bool optimistic,
+                                                   bool bwd) {
+    if (bwd) return reserve_dequeue(q, k, true);
+    uint32_t e = reserve_dequeue(q, k, optimistic);
+    for (int again = 0; e == 0 && again < 3; ++again) {
+        if (ld_rlx(reinterpret_cast<long long*>(&q.ctrl->count.v)) <= 0) break;
+        e = reserve_dequeue(q, k, false);
+    }
+    return e;
+}
+
 // Alg. 1 ENQUEUE's Full test and DEQUEUE's Empty test, read on 64-bit
 // positions: Full when tail - head >= N, Empty when head >= tail.
 __device__ __forceinline__ bool looks_full(const Queue& q) {

@@ -27,6 +27,7 @@ struct Launch {
     int wg_count;
     int batch;                 // ticket_batch b
     int row_chunk;             // solver row chunk (edges)
+    int segments;              // solver queue segments (0 = default)
     uint32_t flags;
     unsigned long long limit;  // watchdog, 100 MHz ticks
 };

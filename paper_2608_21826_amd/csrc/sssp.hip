@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include "csr_device.hpp"
 #include "host_common.hpp"
 #include "sssp_device.hpp"
 
@@ -56,7 +57,8 @@ __global__ __launch_bounds__(INIT_WG) void k_init(Queue q, long long* key, int n
     c->error.v = 0ull;
     c->negcycle.v = 0ull;
     c->aux[0].v = (unsigned long long)gridDim.x;  // number of weight-range partials
-    c->aux[2].v = c->head.v;                      // dequeue position at start
+    for (unsigned sg = 0; sg < MAX_SEG; ++sg)      // dequeue positions at start
+        q.ctrl[sg].aux[2].v = q.ctrl[sg].head.v;
     c->aux[4].v = bq::now_ticks();                // clock at start
     for (int i = 0; i < bq::ST_N; ++i) c->stats[i].v = 0ull;
     // enqueue src: the queue is quiescent, so slot (tail mod N) is free for
@@ -69,20 +71,8 @@ __global__ __launch_bounds__(INIT_WG) void k_init(Queue q, long long* key, int n
     c->count.v = 1ull;
 }
 
-// CSR checks (flag BQ_F_VALIDATE): aux[3] becomes non-zero on a defect.
-__global__ void k_validate(const long long* off, const int* col, int n, long long m,
-                           bq::Ctrl* ctrl) {
-    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    bool bad = false;
-    if (tid == 0) bad = off[0] != 0 || off[n] != m;
-    for (long long v = tid; v < n; v += stride) bad |= off[v + 1] < off[v];
-    for (long long e = tid; e < m; e += stride) bad |= (unsigned)col[e] >= (unsigned)n;
-    if (__any(bad) && bq::lane_id() == 0) bq::st_rlx(&ctrl->aux[3].v, 1ull);
-}
-
 template <int B>
-__global__ __launch_bounds__(SOLVE_WG) void k_solve(SolveArgs a) {
+__global__ __launch_bounds__(SOLVE_WG, SSSP_MIN_WAVES) void k_solve(SolveArgs a) {
     __shared__ WaveLds<B> lds[WAVES_PER_WG];
     __shared__ WgShared S;
     WaveLds<B>& L = lds[threadIdx.x >> 6];
@@ -98,13 +88,19 @@ __global__ __launch_bounds__(SOLVE_WG) void k_solve(SolveArgs a) {
     flush_stats(a.q.ctrl->stats, st);
 }
 
-// dist[v] = d, pred[v] = parent (INT64_MAX / -1 when unreached; pred[src] = -1)
+// dist[v] = d, pred[v] = parent (INT64_MAX / -1 when unreached; pred[src] = -1;
+// INT64_MIN / -1 for minus infinity)
 __global__ void k_unpack(long long* key, int* pred, int n, int src, unsigned shift) {
     const long long dmax = KEY_INF >> shift;
     const unsigned pmask = (1u << (shift - 1u)) - 1u;
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (long long)gridDim.x * blockDim.x) {
         const long long k = key[v];
+        if (is_neg_key(k)) {  // minus infinity (marking mode)
+            key[v] = LLONG_MIN;
+            if (pred) pred[v] = -1;
+            continue;
+        }
         const long long d = k >> shift;
         const bool reached = d != dmax;
         key[v] = reached ? d : LLONG_MAX;
@@ -145,8 +141,9 @@ constexpr unsigned MAX_CHUNK_LOG = 16;
 constexpr int TRACE_CAP = 4096;
 
 bq_status ctx_reset_queue(sssp_ctx* c, hipStream_t s) {
-    BQ_HIP_TRY(hipMemsetAsync(c->slots, 0, sizeof(unsigned long long) * c->capacity, s));
-    BQ_HIP_TRY(hipMemsetAsync(c->ctrl, 0, sizeof(bq::Ctrl), s));
+    BQ_HIP_TRY(hipMemsetAsync(c->slots, 0,
+                              sizeof(unsigned long long) * c->capacity * MAX_SEG, s));
+    BQ_HIP_TRY(hipMemsetAsync(c->ctrl, 0, sizeof(bq::Ctrl) * MAX_SEG, s));
     c->dirty = false;
     return BQ_OK;
 }
@@ -186,19 +183,32 @@ int default_grid(int n, long long m, int max_grid) {
     return g < max_grid ? g : max_grid;
 }
 
+// co-resident workgroups of k_solve<B> (slot 0, 1, 2 for B = 64, 128, 256)
 template <int B>
-bq_status launch_solve(sssp_ctx* c, const SolveArgs& args, const bqh::Launch& L, hipStream_t s,
-                       int slot, int* grid_out) {
+bq_status solve_max_grid(sssp_ctx* c, int slot, int* out) {
     int& per_cu = c->solve_per_cu[slot];
     if (per_cu == 0) {
         BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<B>, SOLVE_WG, 0));
         if (per_cu < 1) per_cu = 1;
     }
-    const int max_grid = per_cu * bqh::device_cus();
-    int grid = L.wg_count > 0 ? L.wg_count : default_grid(args.n, args.m, max_grid);
-    if (grid > max_grid) grid = max_grid;  // all waves co-resident
-    *grid_out = grid;
-    hipLaunchKernelGGL(k_solve<B>, dim3(grid), dim3(SOLVE_WG), 0, s, args);
+    *out = per_cu * bqh::device_cus();
+    return BQ_OK;
+}
+
+bq_status max_grid_for(sssp_ctx* c, int batch, int* out) {
+    switch (batch) {
+        case 1: return solve_max_grid<64>(c, 0, out);
+        case 2: return solve_max_grid<128>(c, 1, out);
+        default: return solve_max_grid<256>(c, 2, out);
+    }
+}
+
+bq_status launch_solve(const SolveArgs& args, int batch, int grid, hipStream_t s) {
+    switch (batch) {
+        case 1: hipLaunchKernelGGL(k_solve<64>, dim3(grid), dim3(SOLVE_WG), 0, s, args); break;
+        case 2: hipLaunchKernelGGL(k_solve<128>, dim3(grid), dim3(SOLVE_WG), 0, s, args); break;
+        default: hipLaunchKernelGGL(k_solve<256>, dim3(grid), dim3(SOLVE_WG), 0, s, args); break;
+    }
     BQ_HIP_TRY(hipGetLastError());
     return BQ_OK;
 }
@@ -230,11 +240,11 @@ bq_status sssp_ctx_create(int32_t max_n, int64_t max_m, sssp_ctx** out) {
     c->capacity = (uint32_t)cap;
     c->logN = bqh::log2_exact(cap);
     const size_t chunks = (size_t)((unsigned long long)max_m >> MIN_CHUNK_LOG) + 1;
-    if (hipMalloc(&c->slots, sizeof(unsigned long long) * cap) != hipSuccess ||
+    if (hipMalloc(&c->slots, sizeof(unsigned long long) * cap * MAX_SEG) != hipSuccess ||
         hipMalloc(&c->trace, sizeof(unsigned long long) * 4 * TRACE_CAP) != hipSuccess ||
         hipHostMalloc(&c->h_trace, sizeof(unsigned long long) * 4 * TRACE_CAP,
                       hipHostMallocDefault) != hipSuccess ||
-        hipMalloc(&c->ctrl, sizeof(bq::Ctrl)) != hipSuccess ||
+        hipMalloc(&c->ctrl, sizeof(bq::Ctrl) * MAX_SEG) != hipSuccess ||
         hipMalloc(&c->chunk_owner, sizeof(unsigned) * chunks) != hipSuccess ||
         hipMalloc(&c->wrange, sizeof(int) * 2 * INIT_MAX_BLOCKS) != hipSuccess ||
         hipHostMalloc(&c->h_ctrl, sizeof(bq::Ctrl), hipHostMallocDefault) != hipSuccess) {
@@ -282,20 +292,19 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
     bq_launch L = {};
     if (base) L = *base;
     L.flags &= ~(uint32_t)(BQ_F_TRACE | BQ_F_VALIDATE);
-    int per_cu = c->solve_per_cu[0];
-    if (per_cu == 0) {
-        BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<64>, SOLVE_WG, 0));
-        if (per_cu < 1) per_cu = 1;
-        c->solve_per_cu[0] = per_cu;
+    int max_grid = 0;
+    {
+        bq_status st = max_grid_for(c, 1, &max_grid);
+        if (st != BQ_OK) return st;
     }
-    const int max_grid = per_cu * bqh::device_cus();
     double best = 1e300;
     bq_launch bestL = L;
-    auto trial = [&](int wgs, int b, double* out_ms, int chunk = -1) -> bq_status {
+    auto trial = [&](int wgs, int b, double* out_ms, int chunk = -1, int seg = -1) -> bq_status {
         bq_launch t = L;
         t.wg_count = wgs;
         t.ticket_batch = b;
         if (chunk >= 0) t.row_chunk = chunk;
+        if (seg >= 0) t.segments = seg;
         double tmin = 1e300;
         for (int r = 0; r < reps; ++r) {
             int32_t neg = 0;
@@ -340,6 +349,17 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
         for (int chunk : {256, 4096}) {
             double ms = 0;
             bq_status st = trial(cur.wg_count, cur.ticket_batch, &ms, chunk);
+            if (st != BQ_OK) return st;
+        }
+    }
+    // queue segments at the best shape: one queue, or 2 / 4 instead of the
+    // default (one per XCD)
+    {
+        const bq_launch cur = bestL;
+        for (int seg : {1, 2, 4}) {
+            if (seg >= cur.wg_count) continue;
+            double ms = 0;
+            bq_status st = trial(cur.wg_count, cur.ticket_batch, &ms, cur.row_chunk, seg);
             if (st != BQ_OK) return st;
         }
     }
@@ -388,15 +408,26 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     const Queue q = ctx_queue(c);
     if (L.flags & BQ_F_VALIDATE) {
         BQ_HIP_TRY(hipMemsetAsync(&c->ctrl->aux[3].v, 0, 8, s));
-        hipLaunchKernelGGL(k_validate, dim3(grid_for((int)(m > n ? (m > INT_MAX ? INT_MAX : m) : n))),
+        hipLaunchKernelGGL(k_validate_csr,
+                           dim3(grid_for((int)(m > n ? (m > INT_MAX ? INT_MAX : m) : n))),
                            dim3(256), 0, s, (const long long*)d_offsets, (const int*)d_cols, n,
-                           (long long)m, c->ctrl);
+                           (long long)m, &c->ctrl->aux[3].v);
         BQ_HIP_TRY(hipGetLastError());
         unsigned long long bad = 0;
         BQ_HIP_TRY(hipMemcpyAsync(&bad, &c->ctrl->aux[3].v, 8, hipMemcpyDeviceToHost, s));
         BQ_HIP_TRY(hipStreamSynchronize(s));
         if (bad) return BQ_EINVAL;
     }
+    int max_grid = 0;
+    {
+        bq_status st = max_grid_for(c, L.batch, &max_grid);
+        if (st != BQ_OK) return st;
+    }
+    int grid = L.wg_count > 0 ? L.wg_count : default_grid(n, (long long)m, max_grid);
+    if (grid > max_grid) grid = max_grid;  // all waves co-resident
+    int nseg = L.segments > 0 ? L.segments : (grid < (int)MAX_SEG ? grid : (int)MAX_SEG);
+    if (nseg > (int)MAX_SEG) return BQ_EINVAL;
+    if (L.flags & BQ_F_TRACE) nseg = 1;  // the timeline follows one queue
     const unsigned shift = key_shift(n);
     SolveArgs a;
     a.q = q;
@@ -416,6 +447,9 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     a.trace = nullptr;
     a.trace_shift = 0;
     a.trace_cap = TRACE_CAP;
+    a.bwd = (L.flags & BQ_F_BWD) ? 1u : 0u;
+    a.nseg = (unsigned)nseg;
+    a.neginf = (L.flags & BQ_F_NEGINF) ? 1u : 0u;
     if (L.flags & BQ_F_TRACE) {
         // about 256 samples per n + m/C items of work
         unsigned long long unit = (unsigned long long)n + ((unsigned long long)m >> clog);
@@ -437,15 +471,11 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
                            c->wrange);
         BQ_HIP_TRY(hipGetLastError());
     }
-    int grid = 0;
-    bq_status st;
     BQ_HIP_TRY(hipEventRecord(c->evs0, s));
-    switch (L.batch) {
-        case 1: st = launch_solve<64>(c, a, L, s, 0, &grid); break;
-        case 2: st = launch_solve<128>(c, a, L, s, 1, &grid); break;
-        default: st = launch_solve<256>(c, a, L, s, 2, &grid); break;
+    {
+        bq_status st = launch_solve(a, L.batch, grid, s);
+        if (st != BQ_OK) return st;
     }
-    if (st != BQ_OK) return st;
     BQ_HIP_TRY(hipEventRecord(c->evs1, s));
     hipLaunchKernelGGL(k_unpack, dim3(grid_for(n)), dim3(256), 0, s, (long long*)d_dist,
                        (int*)d_pred, n, src, shift);
@@ -478,7 +508,7 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     c->last.wg_size = SOLVE_WG;
     const unsigned long long err = h->error.v;
     const bool neg = h->negcycle.v != 0ull;
-    if (err != 0ull || neg || h->abort.v != 0ull) c->dirty = true;  // queue not quiescent
+    if (err != 0ull || h->abort.v != 0ull) c->dirty = true;  // queue not quiescent
     if (err == bq::ERR_RANGE) return BQ_ERANGE;
     if (err != 0ull) return BQ_ETIMEOUT;
     *h_neg_cycle = neg ? 1 : 0;

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(BINIT_WG) void k_binit(const InstDesc* D, const Uni
 }
 
 template <int B>
-__global__ __launch_bounds__(SOLVE_WG) void k_bsolve(const InstDesc* D, int count,
+__global__ __launch_bounds__(SOLVE_WG, SSSP_MIN_WAVES) void k_bsolve(const InstDesc* D, int count,
                                                      const int* claim, int n_claim,
                                                      BatchCtl* bc) {
     __shared__ WaveLds<B> lds[WAVES_PER_WG];
@@ -172,6 +172,12 @@ __global__ void k_bunpack(const InstDesc* D, const Unit* units, int n_units,
         unsigned long long redges = 0;
         for (long long v = un.v0 + threadIdx.x; v < un.v1; v += blockDim.x) {
             const long long k = a.key[v];
+            if (is_neg_key(k)) {  // minus infinity (marking mode)
+                a.key[v] = LLONG_MIN;
+                redges += (unsigned long long)(a.off[v + 1] - a.off[v]);
+                if (d.pred) d.pred[v] = -1;
+                continue;
+            }
             const long long dd = k >> a.shift;
             const bool reached = dd != dmax;
             a.key[v] = reached ? dd : LLONG_MAX;
@@ -459,6 +465,9 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         a.trace = nullptr;
         a.trace_shift = 0;
         a.trace_cap = 0;
+        a.bwd = (L.flags & BQ_F_BWD) ? 1u : 0u;
+        a.nseg = 1;  // one queue per query
+        a.neginf = (L.flags & BQ_F_NEGINF) ? 1u : 0u;
         d.pred = (int*)x.pred;
         d.orig = i;
         d.unit_begin = n_units;

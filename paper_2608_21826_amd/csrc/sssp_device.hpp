@@ -33,14 +33,38 @@
 // [jC, (j+1)C) and enqueues the later chunks of its row as items n + j, which
 // other waves take (chunk_owner[j] = u names the vertex).
 //
-// Termination: `pending` counts items enqueued or being processed; a wave
-// leaves when the queue is empty and pending is 0.
+// Queue segments (the paper's partitioned queue of Section III.B, applied
+// to the chip's XCDs instead of to GPUs): the single-query solver may split
+// its queue into up to 8 Broker Queues, each with its own ring, head, tail
+// and count on separate lines. Workgroups are dispatched to the XCDs in
+// turn, so workgroup i calls segment i mod nseg home: its waves publish
+// there and dequeue there first, and take from the fullest other segment
+// when home is empty. Each hot word then carries 1/nseg of the traffic.
+// Every segment can hold all items, so no enqueue ever finds one Full.
+//
+// Termination: the global counter `pending` equals the live items
+// (published and not yet fully processed) plus every wave's debt: the items
+// a wave retired without subtracting them yet. A wave pays a publish of k
+// items out of its debt when it can and adds only the rest to pending, and
+// gives its whole debt back before it waits for work. The counter is raised
+// before items become visible, so it is 0 only when no item is live and no
+// wave holds debt: then the work is done. While the queue is busy most
+// batches publish about as much as they retire, so pending sees few atomics.
 //
 // Negative cycles (Alg. 3 detects them as changes in round n-1; a queue has
 // no rounds): (1) a label below (n-1) * min(0, min w) is impossible without
 // one; (2) once the dequeued work exceeds a few times n, some waves walk the
 // parent pointers (Brent's cycle finding); a closed walk of real edges whose
 // weights sum below zero proves a negative cycle reachable from src.
+// Marking mode (minus infinity) does not stop there: a candidate below the
+// bound, or the vertex a walk found on a negative cycle, takes the key
+// KEY_NEG, which is below every label. A dequeued minus-infinity vertex
+// hands every out-neighbour a candidate below the bound, so the mark spreads
+// through the queue like any lowered label, over exactly the vertices that a
+// negative cycle reaches. When the queue empties, every reachable negative
+// cycle holds a marked vertex (otherwise its edges would all be satisfied
+// and their slacks, which sum to the cycle's weight, could not be negative),
+// and the unmarked labels are exact.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <limits.h>
@@ -52,11 +76,20 @@ namespace {
 using bq::Queue;
 
 constexpr long long KEY_INF = 0x7FFFFFFFFFFFFFFELL;  // d = max, parent = all ones, q = 0
+// minus infinity (marking mode): below every packed label; q = 1 while queued
+constexpr long long KEY_NEG = LLONG_MIN | 1ll;
+
+__device__ __forceinline__ bool is_neg_key(long long k) { return k <= KEY_NEG; }
 constexpr int SOLVE_WG = 256;
 constexpr int WAVES_PER_WG = SOLVE_WG / 64;
 constexpr int OUTCAP = 1024;  // LDS push buffer per wave
 #ifndef SSSP_UNROLL
 #define SSSP_UNROLL 8
+#endif
+// waves per SIMD the solver kernels are compiled for (register budget:
+// 512 / SSSP_MIN_WAVES per lane)
+#ifndef SSSP_MIN_WAVES
+#define SSSP_MIN_WAVES 2
 #endif
 constexpr int U = SSSP_UNROLL;  // edges per lane per pipelined step
 
@@ -78,7 +111,22 @@ struct SolveArgs {
     unsigned long long* trace;    // optional timeline: 4 words per sample
     unsigned trace_shift;         // one sample per 2^trace_shift dequeued items
     unsigned trace_cap;           // samples
+    unsigned bwd;                 // dequeue broker policy: 0 Broker Queue, 1 BWD
+    unsigned nseg;                // queue segments, 1..MAX_SEG (segment s: slots
+                                  // q.slots + s * q.N, control block q.ctrl + s)
+    unsigned neginf;              // 1: mark minus infinity instead of stopping
 };
+
+constexpr unsigned MAX_SEG = 8;  // gfx950: one segment per XCD
+
+// view of queue segment s (segment 0's control block holds the global words:
+// pending, abort, error, negcycle, stats)
+__device__ __forceinline__ Queue seg_queue(const SolveArgs& a, unsigned s) {
+    Queue q = a.q;
+    q.slots = a.q.slots + (unsigned long long)s * a.q.N;
+    q.ctrl = a.q.ctrl + s;
+    return q;
+}
 
 __device__ __forceinline__ long long pack_key(long long d, unsigned parent, unsigned shift) {
     return (long long)(((unsigned long long)d << shift) | ((unsigned long long)parent << 1) | 1ull);
@@ -98,46 +146,50 @@ struct WaveLds {
     int fanpre[65];
 };
 
-// Publish `cnt` items from the wave's LDS buffer (Alg. 1 ENQUEUE for all of
-// them at once). pending is raised by `cnt + pending_delta` before any item
-// becomes visible. `release` orders earlier plain stores (the chunk table)
-// before the items. Returns false on abort.
+// Publish `cnt` items from the wave's LDS buffer into queue segment `seg`
+// (Alg. 1 ENQUEUE for all of them at once). The wave's debt (retired items
+// not yet subtracted from pending, wave-uniform) pays for the items first;
+// pending is raised by the rest before any item becomes visible. `release`
+// orders earlier plain stores (the chunk table) before the items. Returns
+// false on abort.
 template <class LDS>
-__device__ bool flush_out(const SolveArgs& a, LDS& L, int cnt, long long pending_delta,
-                          bool release, unsigned long long& spins) {
+__device__ bool flush_out(const SolveArgs& a, const Queue& seg, LDS& L, int cnt,
+                          long long& debt, bool release, unsigned long long& spins) {
     const Queue& q = a.q;
     const int lane = bq::lane_id();
-    if (cnt == 0) {
-        if (pending_delta != 0 && lane == 0)
-            bq::add_rlx(&q.ctrl->pending.v, (unsigned long long)pending_delta);
-        return true;
-    }
+    if (cnt == 0) return true;
+    const long long need = (long long)cnt - debt;
     unsigned long long base = 0;
     if (lane == 0) {
         // pending, ENSURE on count and the tail positions as three atomics in
         // flight together. In the solver the broker reservation cannot fail:
         // a vertex holds at most one queue item (its q bit) and chunk items
-        // are bounded, and the capacity is twice that, so count + cnt <= N
+        // are bounded, and each segment holds twice that, so count + cnt <= N
         // always; an overflow would be a bug and stops the solve.
-        // a batch that publishes as many items as it retires leaves pending
-        // unchanged: the new items take the place of the retired ones
-        if ((long long)cnt + pending_delta != 0)
-            bq::add_rlx(&q.ctrl->pending.v, (unsigned long long)((long long)cnt + pending_delta));
-        const long long old = bq::add_rlx(reinterpret_cast<long long*>(&q.ctrl->count.v),
+        if (need > 0) bq::add_rlx(&q.ctrl->pending.v, (unsigned long long)need);
+        const long long old = bq::add_rlx(reinterpret_cast<long long*>(&seg.ctrl->count.v),
                                           (long long)cnt);
-        base = bq::add_rlx(&q.ctrl->tail.v, (unsigned long long)cnt);
-        if (old + cnt > (long long)q.N) bq::raise_error(q, bq::ERR_FULL);
+        base = bq::add_rlx(&seg.ctrl->tail.v, (unsigned long long)cnt);
+        if (old + cnt > (long long)seg.N) bq::raise_error(q, bq::ERR_FULL);
     }
+    debt = need > 0 ? 0 : -need;
     base = bq::bcast64(base);
     if (bq::aborted(q)) return false;
     if (release) bq::fence_release();
     for (int c0 = 0; c0 < cnt; c0 += 64) {
         const int i = c0 + lane;
-        if (!bq::put_slots(q, i < cnt, base + (unsigned long long)i, i < cnt ? L.out[i] : 0u,
+        if (!bq::put_slots(seg, i < cnt, base + (unsigned long long)i, i < cnt ? L.out[i] : 0u,
                            a.limit, spins))
             return false;
     }
     return true;
+}
+
+// Give the wave's debt back to pending (before it waits for work).
+__device__ __forceinline__ void pay_debt(const SolveArgs& a, long long& debt) {
+    if (debt != 0 && bq::lane_id() == 0)
+        bq::add_rlx(&a.q.ctrl->pending.v, (unsigned long long)(-debt));
+    debt = 0;
 }
 
 // largest idx in [0, e) with pre[idx] <= t (pre[0] = 0, pre non-decreasing)
@@ -153,9 +205,12 @@ __device__ __forceinline__ int find_item(const int* pre, int e, int t) {
     return lo;
 }
 
+// parent field of x's key; the none sentinel for unreached and minus-infinity
 __device__ __forceinline__ unsigned parent_of(const SolveArgs& a, int x) {
-    const unsigned long long k = (unsigned long long)bq::ld_rlx(&a.key[x]);
-    return (unsigned)((k >> 1) & ((1ull << (a.shift - 1u)) - 1ull));
+    const long long k = bq::ld_rlx(&a.key[x]);
+    const unsigned long long mask = (1ull << (a.shift - 1u)) - 1ull;
+    if (is_neg_key(k)) return (unsigned)mask;
+    return (unsigned)(((unsigned long long)k >> 1) & mask);
 }
 
 // minimum weight over edges p -> y (whole wave scans row p); LLONG_MAX if none
@@ -172,14 +227,15 @@ __device__ long long min_edge(const SolveArgs& a, unsigned p, unsigned y) {
 }
 
 // Brent's cycle search on the parent pointers from x0; on a cycle, sum the
-// lightest edge of every parent step around it. Wave-uniform.
-__device__ bool walk_finds_negative_cycle(const SolveArgs& a, int x0, unsigned budget) {
+// lightest edge of every parent step around it. Returns a vertex of a cycle
+// of negative weight, or -1. Wave-uniform.
+__device__ int walk_finds_negative_cycle(const SolveArgs& a, int x0, unsigned budget) {
     const unsigned sent = (1u << (a.shift - 1u)) - 1u;
     unsigned power = 1, lam = 1, steps = 0;
     unsigned tort = (unsigned)x0;
     unsigned hare = bq::bcast32(parent_of(a, x0));
     while (tort != hare) {
-        if (hare == sent) return false;
+        if (hare == sent) return -1;
         if (power == lam) {
             tort = hare;
             power <<= 1;
@@ -187,22 +243,22 @@ __device__ bool walk_finds_negative_cycle(const SolveArgs& a, int x0, unsigned b
         }
         hare = bq::bcast32(parent_of(a, (int)hare));
         ++lam;
-        if (++steps > budget) return false;
-        if ((steps & 255u) == 0u && bq::aborted(a.q)) return false;
+        if (++steps > budget) return -1;
+        if ((steps & 255u) == 0u && bq::aborted(a.q)) return -1;
     }
-    if (hare == sent) return false;
+    if (hare == sent) return -1;
     // verify: follow lam parent steps from hare, they must close the walk
     long long sum = 0;
     unsigned y = hare;
     for (unsigned i = 0; i < lam; ++i) {
         const unsigned p = bq::bcast32(parent_of(a, (int)y));
-        if (p == sent) return false;
+        if (p == sent) return -1;
         const long long wmin = min_edge(a, p, y);
-        if (wmin == LLONG_MAX) return false;
+        if (wmin == LLONG_MAX) return -1;
         sum += wmin;
         y = p;
     }
-    return y == hare && sum < 0;
+    return (y == hare && sum < 0) ? (int)hare : -1;
 }
 
 // Per-workgroup parking of idle waves: one wave of the workgroup (the
@@ -248,15 +304,18 @@ __device__ int idle_wait(const SolveArgs& a, WgShared& S, int wid, unsigned long
             int level = 0;
             while (true) {
                 ++polls;
-                unsigned long long pend = 0, cnt = 0, hd = 0;
-                if (lane == 0) {
-                    pend = bq::ld_rlx(&q.ctrl->pending.v);
-                    cnt = bq::ld_rlx(&q.ctrl->count.v);
-                    hd = bq::ld_rlx(&q.ctrl->head.v);
+                // lane s < nseg watches segment s; progress = sum of heads
+                unsigned long long pend = 0, hd = 0;
+                long long cnt = 0;
+                if ((unsigned)lane < a.nseg) {
+                    const bq::Ctrl* c = q.ctrl + lane;
+                    cnt = bq::ld_rlx(reinterpret_cast<const long long*>(&c->count.v));
+                    hd = bq::ld_rlx(&c->head.v);
                 }
+                if (lane == 0) pend = bq::ld_rlx(&q.ctrl->pending.v);
                 pend = bq::bcast64(pend);
-                cnt = bq::bcast64(cnt);
-                hd = bq::bcast64(hd);
+                const bool items = __any(cnt > 0);
+                for (int off = 32; off > 0; off >>= 1) hd += __shfl_xor(hd, off, 64);
                 if (pend == 0ull) {
                     if (lane == 0) {
                         wg_st(&S.done, 1);
@@ -264,7 +323,7 @@ __device__ int idle_wait(const SolveArgs& a, WgShared& S, int wid, unsigned long
                     }
                     return 1;
                 }
-                if ((long long)cnt > 0) {
+                if (items) {
                     if (lane == 0) {
                         __hip_atomic_fetch_add(&S.wake, 1u, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -352,7 +411,12 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, in
         wmin = lo;
         wmax = hi;
     }
-    const unsigned long long head0 = bq::ld_rlx(&q.ctrl->aux[2].v);
+    // segments: home by workgroup (the XCD it runs on); lane s holds the
+    // dequeue position where segment s started this solve
+    const unsigned home = blockIdx.x % a.nseg;
+    const Queue hq = seg_queue(a, home);
+    const unsigned long long head0_lane =
+        (unsigned)lane < a.nseg ? bq::ld_rlx(&(q.ctrl + lane)->aux[2].v) : 0ull;
     long long maxabs = 0;
     if (a.m > 0) {
         maxabs = wmax > -wmin ? wmax : -wmin;
@@ -380,6 +444,8 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, in
     bq::Watch idle;
     idle.arm(a.limit);
     unsigned long long seen_head = 0;
+    long long debt = 0;  // retired items not yet taken off pending (wave-uniform)
+    bool flagged = false;  // marking mode: this wave already raised negcycle
 
     while (true) {
         if (bq::aborted(q)) break;
@@ -388,16 +454,40 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, in
             break;
         }
         // ---- DEQUEUE up to B items with one reservation -----------------
+        // home segment first; if it is empty, the fullest other segment
         unsigned e = 0;
-        unsigned long long base = 0;
-        if (lane == 0) {
-            e = bq::reserve_dequeue(q, (unsigned)B, had_work);
-            if (e) base = bq::add_rlx(&q.ctrl->head.v, (unsigned long long)e);
-        }
+        unsigned sidx = home;
+        if (lane == 0) e = bq::ensure_dequeue(hq, (unsigned)B, had_work, a.bwd != 0);
         e = bq::bcast32(e);
-        had_work = e > 0;
+        if (e == 0 && a.nseg > 1) {
+            long long c = 0;
+            if ((unsigned)lane < a.nseg && (unsigned)lane != home)
+                c = bq::ld_rlx(reinterpret_cast<const long long*>(&(q.ctrl + lane)->count.v));
+            // wave arg-max of (count, lane)
+            long long best = c > 0 ? c : 0;
+            int who = lane;
+            for (int off = 32; off > 0; off >>= 1) {
+                const long long ob = __shfl_xor(best, off, 64);
+                const int ow = __shfl_xor(who, off, 64);
+                if (ob > best || (ob == best && ow < who)) {
+                    best = ob;
+                    who = ow;
+                }
+            }
+            if (best > 0) {
+                sidx = bq::bcast32((unsigned)who);
+                if (lane == 0)
+                    e = bq::ensure_dequeue(seg_queue(a, sidx), (unsigned)B, true, a.bwd != 0);
+                e = bq::bcast32(e);
+            }
+        }
+        const Queue dq = seg_queue(a, sidx);
+        unsigned long long base = 0;
+        if (e && lane == 0) base = bq::add_rlx(&dq.ctrl->head.v, (unsigned long long)e);
+        had_work = e > 0 && sidx == home;
         if (e == 0) {
             ++st.idle;
+            pay_debt(a, debt);
             const int r = idle_wait(a, S, wid, seen_head, idle, t_start, st.poll);
             if (r != 0) {
                 result = r;
@@ -415,7 +505,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, in
         for (unsigned c0 = 0; c0 < e; c0 += 64) {
             const unsigned i = c0 + lane;
             unsigned v = 0;
-            if (!bq::read_slots(q, i < e, base + i, v, a.limit, st.spins)) {
+            if (!bq::read_slots(dq, i < e, base + i, v, a.limit, st.spins)) {
                 ok = false;
                 break;
             }
@@ -427,7 +517,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, in
         // the items were published (release fence on that side)
         if (any_chunk) bq::fence_acquire();
         if (a.trace) {
-            const unsigned long long w0 = base - head0, w1 = w0 + e;
+            const unsigned long long w0 = base - head0_lane, w1 = w0 + e;  // one segment
             if ((w0 >> a.trace_shift) != (w1 >> a.trace_shift) && lane == 0) {
                 const unsigned long long idx = w1 >> a.trace_shift;
                 if (idx < a.trace_cap) {
@@ -506,7 +596,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, in
                     }
                     const int cnt_now = (ftot - t0) < 64 ? (ftot - t0) : 64;
                     __builtin_amdgcn_wave_barrier();
-                    if (!flush_out(a, L, cnt_now, 0, true, st.spins)) {
+                    if (!flush_out(a, hq, L, cnt_now, debt, true, st.spins)) {
                         ok = false;
                         break;
                     }
@@ -579,6 +669,10 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, in
                 seen[r] = bkey[r];
                 cd[r] = L.du[bidx[r]] + (long long)bw[r];
                 cand[r] = pack_key(cd[r], (unsigned)L.u[bidx[r]], shift);
+                // marking mode: a candidate below the certain lower bound (or
+                // from a minus-infinity source, whose label is far below it)
+                // proves that a negative cycle reaches the target
+                if (a.neginf && cd[r] < lbound) cand[r] = KEY_NEG;
             }
             if (t0 + 64 * U < total) advance();
             if (t0 + 128 * U < total) fetch(t0 + 128 * U);
@@ -604,16 +698,20 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, in
                 nout += __popcll(pm);
             }
             if (__any(neg)) {
-                if (lane == 0) {
-                    bq::st_rlx(&q.ctrl->negcycle.v, 1ull);
-                    bq::st_rlx(&q.ctrl->abort.v, 1ull);
+                if (!a.neginf) {
+                    if (lane == 0) {
+                        bq::st_rlx(&q.ctrl->negcycle.v, 1ull);
+                        bq::st_rlx(&q.ctrl->abort.v, 1ull);
+                    }
+                    ok = false;
+                    break;
                 }
-                ok = false;
-                break;
+                if (!flagged && lane == 0) bq::st_rlx(&q.ctrl->negcycle.v, 1ull);
+                flagged = true;
             }
             if (nout > OUTCAP - 64 * U) {
                 __builtin_amdgcn_wave_barrier();
-                if (!flush_out(a, L, nout, 0, false, st.spins)) {
+                if (!flush_out(a, hq, L, nout, debt, false, st.spins)) {
                     ok = false;
                     break;
                 }
@@ -624,21 +722,43 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, in
         }
         if (!ok) break;
         __builtin_amdgcn_wave_barrier();
-        // publish the rest and retire this batch in one pending update
-        if (!flush_out(a, L, nout, -(long long)e, false, st.spins)) break;
+        // retire this batch into the debt, then publish the rest
+        debt += (long long)e;
+        if (!flush_out(a, hq, L, nout, debt, false, st.spins)) break;
         st.push += (unsigned long long)nout;
 
         // ---- negative-cycle search once the work looks unbounded --------
-        const unsigned long long work = base + e - head0;
-        if (work > suspect_after && (base - head0) / walk_stride != work / walk_stride) {
+        // work so far, estimated from this segment's dequeue position
+        const unsigned long long h0 = bq::bcast64(__shfl(head0_lane, (int)sidx, 64));
+        const unsigned long long work = (base + e - h0) * a.nseg;
+        const unsigned long long prev = (base - h0) * a.nseg;
+        if (work > suspect_after && prev / walk_stride != work / walk_stride) {
             ++st.walk;
             const unsigned budget = (unsigned)(a.n < (1 << 20) ? a.n + 1 : (1 << 20));
-            if (walk_finds_negative_cycle(a, L.u[0], budget)) {
+            const int hit = walk_finds_negative_cycle(a, L.u[0], budget);
+            if (hit >= 0 && !a.neginf) {
                 if (lane == 0) {
                     bq::st_rlx(&q.ctrl->negcycle.v, 1ull);
                     bq::st_rlx(&q.ctrl->abort.v, 1ull);
                 }
                 break;
+            }
+            if (hit >= 0) {
+                // marking mode: the cycle's vertex becomes minus infinity and
+                // spreads it through the queue like any lowered label
+                long long old = 0;
+                if (lane == 0) {
+                    old = __hip_atomic_fetch_min(&a.key[hit], KEY_NEG, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+                    if (!flagged) bq::st_rlx(&q.ctrl->negcycle.v, 1ull);
+                }
+                flagged = true;
+                old = (long long)bq::bcast64((unsigned long long)old);
+                const int cnt = (KEY_NEG < old && (old & 1ll) == 0) ? 1 : 0;
+                if (lane == 0) L.out[0] = (unsigned)hit;
+                __builtin_amdgcn_wave_barrier();
+                if (!flush_out(a, hq, L, cnt, debt, false, st.spins)) break;
+                st.push += (unsigned long long)cnt;
             }
         }
     }

@@ -83,6 +83,7 @@ def test_mixed_batch_matches_oracle(batch, seed):
 @pytest.mark.parametrize("launch", [
     {"wg_count": 1}, {"wg_count": 3}, {"wg_count": 7, "ticket_batch": 2},
     {"row_chunk": 256}, {"queue_scale": 1}, {"row_chunk": 64, "wg_count": 16},
+    {"flags": 8, "wg_count": 5}, {"flags": 8, "ticket_batch": 4},
 ])
 def test_launch_shapes(batch, launch):
     print(f"[batched] launch {launch}", flush=True)
@@ -103,6 +104,27 @@ def test_negative_cycle_in_the_mix(batch):
     check_all(qs, keep, neg)
     qs2, keep2 = make_queries(mixed_graphs(6, 10))
     check_all(qs2, keep2, batch.solve(qs2))
+
+
+def test_negative_cycle_marking_in_the_mix(batch):
+    """With BQ_F_NEGINF the query with a cycle gets minus infinity where the
+    cycle reaches and exact values elsewhere; the others are exact."""
+    items = mixed_graphs(7, 9)
+    base = synth.potential_random(1200, 9000, seed=61)
+    s, t, w = synth.edges_of(base)
+    n0 = base.n
+    gneg = synth.csr_from_edges(n0 + 3, np.concatenate([s, [17, n0, n0 + 1, n0 + 2]]),
+                                np.concatenate([t, [n0, n0 + 1, n0 + 2, n0]]),
+                                np.concatenate([w, [5, 2, 2, -5]]), source=0)
+    items.insert(3, (gneg, 0, upload(gneg)))
+    qs, keep = make_queries(items)
+    neg = batch.solve(qs, launch={"flags": pkg.BQ_F_NEGINF})
+    assert neg[3] and sum(neg) == 1
+    torch.cuda.synchronize()
+    d_ref, p_ref, _ = oracle.neg_inf(gneg, 0)
+    assert np.array_equal(qs[3][4].cpu().numpy(), d_ref)
+    assert np.array_equal(qs[3][5].cpu().numpy(), p_ref)
+    check_all(qs[:3] + qs[4:], keep[:3] + keep[4:], neg[:3] + neg[4:])
 
 
 def test_shared_graph_many_sources(batch):

@@ -84,6 +84,50 @@ def test_launch_shapes(ctx, b, wgs):
     check(ctx, g, launch={"ticket_batch": b, "wg_count": wgs}, method="fifo")
 
 
+@pytest.mark.parametrize("wgs", [1, 5, 0])
+@pytest.mark.parametrize("b", [1, 4])
+def test_bwd_policy(ctx, wgs, b):
+    """The BWD broker policy changes only how dequeues take from the count;
+    the results are the same."""
+    g = synth.potential_random(20000, 160000, seed=78)
+    check(ctx, g, launch={"ticket_batch": b, "wg_count": wgs, "flags": pkg.BQ_F_BWD},
+          method="fifo")
+
+
+@pytest.mark.parametrize("seg", [1, 2, 3, 8])
+@pytest.mark.parametrize("wgs", [2, 9, 0])
+def test_queue_segments(ctx, seg, wgs):
+    """The queue split into segments (home by workgroup, stealing from the
+    fullest other segment) gives the same results, also with segments that
+    no workgroup calls home."""
+    g = synth.potential_random(20000, 160000, seed=79)
+    check(ctx, g, launch={"segments": seg, "wg_count": wgs, "ticket_batch": 2}, method="fifo")
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_queue_segments_small_negative(ctx, seed):
+    rng = np.random.default_rng(4200 + seed)
+    n = int(rng.integers(1, 80))
+    g = synth.random_small(n, int(rng.integers(0, 5 * n + 1)), -6, 30, seed=4300 + seed)
+    check(ctx, g, src=int(rng.integers(0, n)), launch={"segments": 8, "wg_count": 16})
+
+
+def test_queue_segments_rejects_too_many(ctx):
+    g = synth.grid64()
+    off, col, w = _dev(g)
+    with pytest.raises(pkg.BQError) as e:
+        ctx.solve(off, col, w, 0, launch={"segments": 9})
+    assert e.value.status == pkg.BQ_EINVAL
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_bwd_policy_small_negative(ctx, seed):
+    rng = np.random.default_rng(4000 + seed)
+    n = int(rng.integers(1, 60))
+    g = synth.random_small(n, int(rng.integers(0, 5 * n + 1)), -6, 30, seed=4100 + seed)
+    check(ctx, g, src=int(rng.integers(0, n)), launch={"flags": pkg.BQ_F_BWD})
+
+
 def test_single_vertex_and_no_edges(ctx):
     g = synth.csr_from_edges(1, [], [], [])
     d, p, neg = run(ctx, g)
@@ -136,6 +180,73 @@ def test_planted_negative_cycles(ctx, cyc_len, reachable):
     if not reachable:
         d_ref, p_ref, _ = oracle.sssp(g, method="fifo")
         assert np.array_equal(d, d_ref) and np.array_equal(p, p_ref)
+
+
+# ---------------------------------------------------------------------------
+# minus-infinity marking (BQ_F_NEGINF)
+# ---------------------------------------------------------------------------
+
+def check_neg_inf(ctx, g, src=None, launch=None):
+    src = g.src if src is None else src
+    print(f"[sssp] neg_inf {g.name} n={g.n} m={g.m} src={src} launch={launch}", flush=True)
+    off, col, w = _dev(g)
+    dist, pred, neg = ctx.solve(off, col, w, src, launch=launch, validate=True, neg_inf=True)
+    d, p = dist.cpu().numpy(), pred.cpu().numpy()
+    d_ref, p_ref, neg_ref = oracle.neg_inf(g, src)
+    assert neg == neg_ref
+    bad = np.nonzero(d != d_ref)[0]
+    assert bad.size == 0, f"dist differs at {bad[:5]}: {d[bad[:5]]} vs {d_ref[bad[:5]]}"
+    bad = np.nonzero(p != p_ref)[0]
+    assert bad.size == 0, f"pred differs at {bad[:5]}: {p[bad[:5]]} vs {p_ref[bad[:5]]}"
+    return neg
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_neg_inf_random_small(ctx, seed):
+    rng = np.random.default_rng(8700 + seed)
+    n = int(rng.integers(1, 60))
+    g = synth.random_small(n, int(rng.integers(0, 4 * n + 1)), -6, 30, seed=8800 + seed)
+    launch = {"segments": 8, "wg_count": 16} if seed % 2 else None
+    check_neg_inf(ctx, g, src=int(rng.integers(0, n)), launch=launch)
+
+
+def _cycle_with_tail(cyc_len, seed):
+    base = synth.potential_random(1200, 9000, seed=seed)
+    s, t, w = synth.edges_of(base)
+    n0 = base.n
+    cyc = np.arange(n0, n0 + cyc_len)
+    cw = np.full(cyc_len, 4, dtype=np.int64)
+    cw[-1] = -(4 * (cyc_len - 1)) - 1
+    tail = np.arange(n0 + cyc_len, n0 + cyc_len + 50)
+    ts = np.concatenate([[cyc[0]], tail[:-1]])
+    return synth.csr_from_edges(
+        n0 + cyc_len + 50,
+        np.concatenate([s, [17], cyc, ts]),
+        np.concatenate([t, [cyc[0]], np.roll(cyc, -1), tail]),
+        np.concatenate([w, [5], cw, np.full(50, 2)]), source=0)
+
+
+@pytest.mark.parametrize("cyc_len", [1, 2, 7, 300])
+def test_neg_inf_cycle_with_tail(ctx, cyc_len):
+    g = _cycle_with_tail(cyc_len, 8900 + cyc_len)
+    assert check_neg_inf(ctx, g)
+    assert check_neg_inf(ctx, g, launch={"segments": 1, "ticket_batch": 4})
+
+
+def test_neg_inf_two_cycles_and_no_cycle(ctx):
+    """Two separate negative cycles, each with its own downstream set."""
+    g1 = _cycle_with_tail(3, 8950)
+    s, t, w = synth.edges_of(g1)
+    n = g1.n
+    extra = (np.array([40, n, n + 1, n + 2]), np.array([n, n + 1, n + 2, n]),
+             np.array([1, -2, -2, 3]))
+    g = synth.csr_from_edges(n + 3, np.concatenate([s, extra[0]]),
+                             np.concatenate([t, extra[1]]), np.concatenate([w, extra[2]]),
+                             source=0)
+    assert check_neg_inf(ctx, g)
+    assert check_neg_inf(ctx, synth.road(48, plant_cycle=True, seed=8960))
+    assert not check_neg_inf(ctx, synth.road(48, plant_cycle=False, seed=8960))
+    assert not check_neg_inf(ctx, synth.potential_random(5000, 40000, seed=8961))
 
 
 def test_solve_after_negative_cycle_reuses_context(ctx):
@@ -228,3 +339,15 @@ def test_road2048_planted_negative_cycle(big_ctx):
     d, p, neg = run(big_ctx, g, validate=False)
     print("[sssp] road2048_negcycle stats", big_ctx.stats(), flush=True)
     assert neg
+
+
+def test_road2048_negative_cycle_marks_everything(big_ctx):
+    """The mesh has edges both ways, so the planted cycle reaches every
+    vertex: with marking, every distance is minus infinity (a property that
+    holds at any size; the oracle's n rounds are out of reach here)."""
+    g = synth.config_graph("road2048_negcycle")
+    off, col, w = _dev(g)
+    dist, pred, neg = big_ctx.solve(off, col, w, g.src, neg_inf=True)
+    print("[sssp] road2048_negcycle marking stats", big_ctx.stats(), flush=True)
+    assert neg
+    assert bool((dist == np.iinfo(np.int64).min).all()) and bool((pred == -1).all())
