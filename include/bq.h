@@ -57,7 +57,11 @@ typedef struct sssp_rounds_ctx sssp_rounds_ctx;
 /* Launch shape. Zero fields mean "library default". */
 typedef struct {
     int32_t wg_size;      /* threads per workgroup, multiple of 64 (<= 1024) */
-    int32_t wg_count;     /* workgroups; 0 = fill the chip (occupancy x CUs) */
+    int32_t wg_count;     /* workgroups; 0 = the call's default: queue
+                             benchmarks fill the chip (occupancy x CUs);
+                             sssp_bf and sssp_bf_batched take about one per
+                             16K units of n + m/16 (per query, at least one),
+                             up to the co-resident maximum */
     int32_t ticket_batch; /* b: a wave dequeues up to 64*b items per ticket */
     uint32_t flags;       /* BQ_F_* */
     uint64_t timeout_us;  /* watchdog for a single wait; 0 = 2 s. A solve

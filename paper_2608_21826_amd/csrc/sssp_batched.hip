@@ -418,7 +418,15 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
 
     const int max_grid = batch_max_grid(b, B);
-    int grid = L.wg_count > 0 ? L.wg_count : max_grid;
+    // default: about one workgroup per 16K units of n + m/16 of each query
+    // (the single-query solver's rule), at least one per query; more waves
+    // than the work can feed only raise the relaxations per edge
+    long long want = 0;
+    for (int i = 0; i < count; ++i) {
+        const long long units = (long long)h_inst[i].n + h_inst[i].m / 16;
+        want += units / 16384 > 1 ? units / 16384 : 1;
+    }
+    int grid = L.wg_count > 0 ? L.wg_count : (want < max_grid ? (int)want : max_grid);
     if (grid > max_grid) grid = max_grid;
 
     // layout: queue slots, chunk tables, units, claim list
