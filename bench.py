@@ -64,6 +64,32 @@ def read_traffic(per_launch_units):
         return None
 
 
+L2_FILE = os.path.join(ROOT, "profiles", "l2_hit_rmat20_queue_rounds.txt")
+ATOMICS_FILE = os.path.join(ROOT, "profiles", "atomics_rmat20_queue.txt")
+
+
+def read_counter_summary(path, kernel, key):
+    """One value of a kernel's block in a committed counter summary, or None
+    when the file is missing or was taken on other solver sources."""
+    if not os.path.exists(path):
+        return None
+    cur, rec = None, {}
+    for line in open(path):
+        if line.startswith("#") or "=" not in line:
+            continue
+        k, v = (x.strip() for x in line.split("=", 1))
+        if k == "kernel":
+            cur = v
+        elif cur == kernel:
+            rec[k] = v
+    if rec.get("kernel_source_hash") != kernel_source_hash() or key not in rec:
+        return None
+    try:
+        return float(rec[key])
+    except ValueError:
+        return None
+
+
 def cpu_baseline(g, m_reached, budget_s=12.0):
     """The oracle as it stands (round-based Bellman-Ford, Alg. 3 on one
     processing element, single thread) on the same graph and source, repeated
@@ -248,8 +274,9 @@ def queue_sweep(pkg, steps=2):
     (Global Mixed, Global EnqDeq), both policies (Broker Queue, BWD),
     workgroup sizes 64..1024 (the paper's 32..512 threads per block, in whole
     waves), workgroup counts from the paper's 64/108/216 blocks up to the
-    co-resident grid, and ticket batch b = 1 (one wave op per 64 lanes) and 16.
-    Mixed: 2^20 slots, 2^26 operations. EnqDeq: 2^26 operations on a queue
+    co-resident grid, and ticket batch b = 1 (one wave op per 64 lanes) and 16;
+    plus the partitioned queue (8 segments, one per XCD) under the Broker
+    Queue policy. Mixed: 2^20 slots, 2^26 operations. EnqDeq: 2^26 operations on a queue
     of 2^25 slots, so that every one of the 2^25 enqueues fits and each
     phase moves real items. Returns rows of Mops/s."""
     qm = pkg.Queue(QUEUE_CAP)
@@ -257,12 +284,14 @@ def queue_sweep(pkg, steps=2):
     rows = []
     for scen in ("mixed", "enqdeq"):
         q = qm if scen == "mixed" else qe
-        for bwd in (False, True):
+        for bwd, seg in ((False, 1), (True, 1), (False, 8)):
             for b in (1, 16):
                 for wgsz in (64, 128, 256, 512, 1024):
                     for wgs in (64, 108, 216, 512, 0):
+                        if seg > 1 and wgs in (108, 216):
+                            continue  # not a multiple of 2 x 8 workgroups
                         L = {"ticket_batch": b, "wg_size": wgsz, "wg_count": wgs,
-                             "flags": pkg.BQ_F_BWD if bwd else 0}
+                             "flags": pkg.BQ_F_BWD if bwd else 0, "segments": seg}
                         best = None
                         for _ in range(steps):
                             if scen == "mixed":
@@ -276,6 +305,7 @@ def queue_sweep(pkg, steps=2):
                             if best is None or ms < best[0]:
                                 best = (ms, fails, ok)
                         rows.append({"scenario": scen, "policy": "BWD" if bwd else "BQ", "b": b,
+                                     "segments": seg,
                                      "wg_size": wgsz, "wg_count": wgs, "ms": round(best[0], 3),
                                      "mops": round(QUEUE_OPS / best[0] / 1e3, 1),
                                      "refused": int(best[1]), "ok": int(best[2])})
@@ -360,6 +390,8 @@ def main():
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--sssp-launch", type=str, default=None,
                     help='fixed solver launch as JSON, e.g. {"wg_count":128,"row_chunk":256}')
+    ap.add_argument("--queue-launch", type=str, default=None,
+                    help='fixed queue launch as JSON, e.g. {"ticket_batch":64,"wg_size":1024}')
     ap.add_argument("--no-tune", action="store_true",
                     help="library default launch shapes (no autotuning)")
     ap.add_argument("--sssp-only", action="store_true",
@@ -372,8 +404,8 @@ def main():
                     help="only run the queue scenario / policy / launch-shape sweep")
     ap.add_argument("--bf-sweep", action="store_true",
                     help="only run the solver policy / workgroup-count sweep")
-    ap.add_argument("--probes", action="store_true",
-                    help="measure HBM copy and atomic rates (roofline context)")
+    ap.add_argument("--no-probes", action="store_true",
+                    help="skip the HBM copy and atomic-rate probes (roofline context)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU form of "
@@ -423,7 +455,7 @@ def main():
         del a, b
 
     probes = None
-    if args.probes:
+    if not args.no_probes and not args.sssp_only:
         probes = run_probes(pkg, torch, dev)
         log(f"probes {probes}")
 
@@ -437,7 +469,9 @@ def main():
         log(f"sssp autotune: {sssp_launch} {tune_ms:.3f} ms")
     queue_launch = {"ticket_batch": 1}
     queue_b1_ms = None
-    if not args.sssp_only:
+    if args.queue_launch:
+        queue_launch = json.loads(args.queue_launch)
+    elif not args.sssp_only:
         best = None
         for b in (1, 4, 16, 64):
             for wgsz in (256, 1024):
@@ -454,6 +488,20 @@ def main():
                 break
         queue_launch = best[1]
         log(f"queue launch: {queue_launch} {best[0]:.3f} ms (b=1 best {queue_b1_ms:.3f} ms)")
+    queue_part = None
+    if not args.sssp_only:
+        # the partitioned form (one Broker Queue per XCD, Alg. 2's layout)
+        queue_part = {}
+        for b in (1, 64):
+            best = None
+            for S in (4, 8):
+                L = {"ticket_batch": b, "wg_size": 1024, "wg_count": 0, "segments": S}
+                t = min(q.bench_mixed(QUEUE_OPS, launch=L)[0]["ms"] for _ in range(2))
+                if best is None or t < best[0]:
+                    best = (t, S)
+            queue_part[f"b{b}"] = {"mops": round(QUEUE_OPS / (best[0] * 1e-3) / 1e6, 1),
+                                   "segments": best[1], "ms": round(best[0], 4)}
+        log(f"partitioned queue: {queue_part}")
 
     def step():
         st = {"ms": float("nan"), "enq_full": 0, "deq_empty": 0}
@@ -489,6 +537,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
             "traffic": read_traffic(None), "kernel": "k_solve<64>",
+            "l2_hit_rate": read_counter_summary(L2_FILE, "k_solve", "l2_hit_rate"),
             "algorithmic_bytes_per_launch": int(alg_bytes),
             "kernel_ms": round(float(k_ms.mean()), 4)}
     out = {
@@ -502,6 +551,7 @@ def main():
                    "queue_ops": QUEUE_OPS, "parallelism": "single_gpu"},
         "queue_mops": round(qmops, 2),
         "queue_mops_b1": round(QUEUE_OPS / (queue_b1_ms * 1e-3) / 1e6, 2) if queue_b1_ms else None,
+        "queue_partitioned": queue_part,
         "launch": {"sssp": sssp_launch, "queue": queue_launch},
         "sssp": {"ms": round(float(s_ms.mean()), 4), "ms_median": round(float(np.median(s_ms)), 4),
                  "solver_kernel_ms": round(float(k_ms.mean()), 4),
@@ -515,11 +565,20 @@ def main():
                   "deq_empty": int(qs[-1]["deq_empty"])},
         "roofline": roof,
     }
+    # atomics the solver kernel issues (counter summary of the same sources),
+    # per second of its time, against the measured random-atomicMin rate
+    n_atomics = read_counter_summary(ATOMICS_FILE, "k_solve", "TCC_ATOMIC_sum_mean")
+    if n_atomics:
+        out["atomic_rate_G"] = round(n_atomics / (k_ms.mean() * 1e-3) / 1e9, 3)
     if probes:
         out["probes"] = probes
-        if probes.get("atomic_min_rand_8MiB_Gops"):
-            out["atomic_frac"] = round(
-                (rel / (k_ms.mean() * 1e-3) / 1e9) / probes["atomic_min_rand_8MiB_Gops"], 4)
+        peak = probes.get("atomic_min_rand_8MiB_Gops")
+        if peak:
+            if n_atomics:
+                out["atomic_frac"] = round(out["atomic_rate_G"] / peak, 4)
+            # relaxations are mostly loads (the key check), not atomics
+            out["relax_rate_vs_atomic_peak"] = round(
+                (rel / (k_ms.mean() * 1e-3) / 1e9) / peak, 4)
     if not args.sssp_only:
         out["rounds_form"] = rounds_leg(pkg, torch, g, off, col, w, dist, m_reached)
         log(f"rounds form {out['rounds_form']}")

@@ -78,7 +78,9 @@ typedef struct {
                              publishing to segment i mod segments and taking
                              from the fullest other segment when its own is
                              empty; 0 = min(8, workgroups). Forced to 1 with
-                             BQ_F_TRACE. Other calls ignore it. */
+                             BQ_F_TRACE. bq_bench_mixed / bq_bench_enqdeq:
+                             1, 2, 4 or 8 segments of capacity/segments
+                             slots (0 = 1). Other calls ignore it. */
 } bq_launch;
 
 #define BQ_F_VALIDATE 1u  /* sssp_bf: check the CSR on the device first */
@@ -190,7 +192,9 @@ bq_status bq_dequeue(bq_queue* q, int32_t* d_out, uint64_t n, uint64_t* d_n_ok,
  * for operation i), then n_ops/2 dequeues, each operation one attempt
  * (Successful / Full, data / Empty), chunks of 64*b per wave as in
  * bq_enqueue. The queue is reset to empty first. *h_enq / *h_deq get the
- * counts and kernel times of the two phases. Synchronous. */
+ * counts and kernel times of the two phases. launch->segments S = 2, 4, 8
+ * selects the partitioned form of bq_bench_mixed (segment s carries
+ * operations [s P, (s+1) P), P = n_ops/2 / S). Synchronous. */
 bq_status bq_bench_enqdeq(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
                           bq_bench_stats* h_enq, bq_bench_stats* h_deq, void* stream);
 
@@ -211,7 +215,17 @@ bq_status bq_counters(bq_queue* q, void* stream, uint64_t* h_head, uint64_t* h_t
  * select BQ_F_BWD): value i belongs to
  * chunk c = i / K of enqueuer wave c mod W (W = *h_enq_waves on return),
  * lane (i mod K) mod 64 of that wave, and is that lane's item number
- * (c / W) * b + (i mod K) / 64. Synchronous. */
+ * (c / W) * b + (i mod K) / 64. Synchronous.
+ *
+ * Partitioned form (launch->segments S = 2, 4 or 8; the paper's multi-GPU
+ * queue of Alg. 2 on the chip's XCDs): the queue is split into S Broker
+ * Queues of capacity/S slots each (at least 64*b), workgroup i works on
+ * segment i mod S and enqueues when (i / S) is even; segment s carries
+ * operations [s P, (s+1) P) of each kind, P = n_ops/2 / S (n_ops/2 must be
+ * a multiple of S), and the grid is rounded down to a multiple of 2S. Each
+ * segment is FIFO on its own. The logs hold position p of segment s at index
+ * s P + p; the rule for value i above applies within its segment with
+ * i - s P for i, c = (i - s P) / K and W / S enqueuer waves per segment. */
 bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
                          int32_t* d_enq_log, int32_t* d_deq_log, bq_bench_stats* h_out,
                          int32_t* h_enq_waves, void* stream);

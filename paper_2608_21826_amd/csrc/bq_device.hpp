@@ -146,7 +146,9 @@ __device__ __forceinline__ unsigned long long now_ticks() { return wall_clock64(
 // ---------------------------------------------------------------------------
 struct Queue {
     unsigned long long* slots;  // [N] (ticket << 32 | payload)
-    Ctrl* ctrl;
+    Ctrl* ctrl;                 // head, tail, count of this queue
+    Ctrl* sig;                  // abort / error words (the same block, or the
+                                // first segment's for a segment of a split queue)
     uint32_t logN;
     uint32_t pad;
     unsigned long long N;
@@ -158,15 +160,15 @@ __device__ __forceinline__ unsigned long long slot_word(uint32_t ticket, uint32_
 
 // wave-uniform read of the abort word
 __device__ __forceinline__ bool aborted(const Queue& q) {
-    return bcast64(ld_rlx(&q.ctrl->abort.v)) != 0ull;
+    return bcast64(ld_rlx(&q.sig->abort.v)) != 0ull;
 }
 
 __device__ __forceinline__ void raise_error(const Queue& q, int code) {
     unsigned long long zero = 0ull;
-    __hip_atomic_compare_exchange_strong(&q.ctrl->error.v, &zero, (unsigned long long)code,
+    __hip_atomic_compare_exchange_strong(&q.sig->error.v, &zero, (unsigned long long)code,
                                          __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
-    st_rlx(&q.ctrl->abort.v, 1ull);
+    st_rlx(&q.sig->abort.v, 1ull);
 }
 
 // Watchdog: a wait that lasts longer than `limit` ticks (100 MHz) gives up.

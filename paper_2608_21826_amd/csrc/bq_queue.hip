@@ -14,22 +14,33 @@
 
 using bq::Queue;
 
+// Partitioned form (the paper's multi-GPU queue of Section III.B and Alg. 2
+// on the chip's XCDs): the benchmarks can split the queue into S = 2, 4 or 8
+// segments, each a complete Broker Queue over capacity / S slots with its own
+// control block. Workgroup i works on segment i mod S (workgroups are
+// dispatched to the XCDs in turn), and each segment carries 1/S of the
+// operations, as each GPU does in Alg. 2.
+constexpr unsigned MAX_QSEG = 8;
+
 struct bq_queue {
     int device;
     uint32_t capacity;
     uint32_t logN;
     unsigned long long* slots;   // [capacity] (ticket << 32 | payload)
-    bq::Ctrl* ctrl;
+    bq::Ctrl* ctrl;              // [MAX_QSEG]; block 0 serves the unsegmented queue
     unsigned long long* scratch;  // device counters for the bench
     hipEvent_t ev0, ev1;
 };
 
 namespace {
 
-__device__ __forceinline__ Queue view(unsigned long long* sl, bq::Ctrl* c, uint32_t logN) {
+// `sig`: the control block whose abort / error words stop every segment
+__device__ __forceinline__ Queue view(unsigned long long* sl, bq::Ctrl* c, uint32_t logN,
+                                      bq::Ctrl* sig) {
     Queue q;
     q.slots = sl;
     q.ctrl = c;
+    q.sig = sig;
     q.logN = logN;
     q.pad = 0;
     q.N = 1ull << logN;
@@ -130,20 +141,29 @@ __device__ unsigned long long chunk_op(const Queue& q, unsigned long long first,
 
 // ENQUEUE (ENQ) or DEQUEUE of n operations, grid-stride over chunks of
 // 64*b; every operation makes one attempt (Successful / Full, data / Empty).
+// With lseg > 0 the queue is split into 2^lseg segments (see bq_queue):
+// workgroup i works on segment i mod 2^lseg, and segment s owns operations
+// [s n / 2^lseg, (s+1) n / 2^lseg).
 template <bool ENQ>
 __global__ void k_bulk(unsigned long long* slots, bq::Ctrl* ctrl, uint32_t logN,
                        const int32_t* vals, int32_t* out, unsigned long long n,
                        unsigned long long* n_ok, unsigned long long* stats,
-                       unsigned long long limit, unsigned b, int bwd) {
-    const Queue q = view(slots, ctrl, logN);
-    const unsigned long long waves = (unsigned long long)gridDim.x * (blockDim.x >> 6);
-    const unsigned long long wave = (unsigned long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+                       unsigned long long limit, unsigned b, int bwd, unsigned lseg) {
+    const unsigned S = 1u << lseg;
+    const unsigned seg = blockIdx.x & (S - 1u);
+    const Queue q = view(slots + ((unsigned long long)seg << (logN - lseg)), ctrl + seg,
+                         logN - lseg, ctrl);
+    const unsigned long long wpb = blockDim.x >> 6;
+    const unsigned long long waves = (unsigned long long)(gridDim.x >> lseg) * wpb;
+    const unsigned long long wave = (unsigned long long)(blockIdx.x >> lseg) * wpb + (threadIdx.x >> 6);
+    const unsigned long long per = n >> lseg;  // the host checks n % S == 0
+    const unsigned long long lo = per * seg;
     const unsigned long long K = 64ull * b;
     unsigned long long ok = 0, spins = 0, fails = 0;
     bool bad = false;
-    for (unsigned long long c = wave; c * K < n && !bad; c += waves) {
-        const unsigned long long first = c * K;
-        const unsigned long long cnt = (n - first) < K ? (n - first) : K;
+    for (unsigned long long c = wave; c * K < per && !bad; c += waves) {
+        const unsigned long long first = lo + c * K;
+        const unsigned long long cnt = (per - c * K) < K ? (per - c * K) : K;
         ok += chunk_op<ENQ>(q, first, cnt, vals, out, n_ok, nullptr, bwd != 0, false, limit, spins,
                             fails, bad);
     }
@@ -160,25 +180,39 @@ __global__ void k_bulk(unsigned long long* slots, bq::Ctrl* ctrl, uint32_t logN,
 // state allows; operations that return Full / Empty are retried after a
 // backoff until the chunk is done. Enqueue operation i writes value i.
 // stats[0..3] = enq_ok, deq_ok, enq_full, deq_empty.
+// Partitioned (lseg > 0): workgroup i works on segment s = i mod S and is
+// an enqueuer when (i / S) is even; segment s carries operations
+// [s n_half / S, (s+1) n_half / S) of each kind, and its logs are the same
+// slices of enq_log / deq_log (position P of segment s at index
+// s n_half / S + P).
 __global__ void k_bench_mixed(unsigned long long* slots, bq::Ctrl* ctrl, uint32_t logN,
                               unsigned long long n_half, int32_t* enq_log, int32_t* deq_log,
                               unsigned long long* stats, unsigned long long limit, unsigned b,
-                              int bwd) {
-    const Queue q = view(slots, ctrl, logN);
+                              int bwd, unsigned lseg) {
+    const unsigned S = 1u << lseg;
+    const unsigned seg = blockIdx.x & (S - 1u);
+    const unsigned rank = blockIdx.x >> lseg;  // workgroup's rank in its segment
+    const Queue q = view(slots + ((unsigned long long)seg << (logN - lseg)), ctrl + seg,
+                         logN - lseg, ctrl);
     const int wpb = blockDim.x >> 6;
-    const bool enq = (blockIdx.x & 1u) == 0u;
-    const unsigned long long role_blocks = enq ? (gridDim.x + 1u) / 2u : gridDim.x / 2u;
+    const unsigned gps = gridDim.x >> lseg;    // the host makes grid a multiple of 2S
+    const bool enq = (rank & 1u) == 0u;
+    const unsigned long long role_blocks = enq ? (gps + 1u) / 2u : gps / 2u;
     const unsigned long long waves = role_blocks * (unsigned long long)wpb;
-    const unsigned long long wave = (unsigned long long)(blockIdx.x >> 1) * wpb + (threadIdx.x >> 6);
+    const unsigned long long wave = (unsigned long long)(rank >> 1) * wpb + (threadIdx.x >> 6);
+    const unsigned long long per = n_half >> lseg;  // the host checks n_half % S == 0
+    const unsigned long long lo = per * seg;
+    int32_t* elog = enq_log ? enq_log + lo : nullptr;
+    int32_t* dlog = deq_log ? deq_log + lo : nullptr;
     const unsigned long long K = 64ull * b;
     unsigned long long ok = 0, spins = 0, fails = 0;
     bool bad = false;
-    for (unsigned long long c = wave; c * K < n_half && !bad; c += waves) {
-        const unsigned long long first = c * K;
-        const unsigned long long cnt = (n_half - first) < K ? (n_half - first) : K;
-        ok += enq ? chunk_op<true>(q, first, cnt, nullptr, nullptr, nullptr, enq_log, bwd != 0,
+    for (unsigned long long c = wave; c * K < per && !bad; c += waves) {
+        const unsigned long long first = lo + c * K;
+        const unsigned long long cnt = (per - c * K) < K ? (per - c * K) : K;
+        ok += enq ? chunk_op<true>(q, first, cnt, nullptr, nullptr, nullptr, elog, bwd != 0,
                                    true, limit, spins, fails, bad)
-                  : chunk_op<false>(q, first, cnt, nullptr, nullptr, nullptr, deq_log, bwd != 0,
+                  : chunk_op<false>(q, first, cnt, nullptr, nullptr, nullptr, dlog, bwd != 0,
                                     true, limit, spins, fails, bad);
     }
     if (bq::lane_id() == 0) {
@@ -242,8 +276,18 @@ int32_t bq_device_cus(void) { return bqh::device_cus(); }
 
 static bq_status queue_zero(bq_queue* q, hipStream_t s) {
     BQ_HIP_TRY(hipMemsetAsync(q->slots, 0, sizeof(unsigned long long) * q->capacity, s));
-    BQ_HIP_TRY(hipMemsetAsync(q->ctrl, 0, sizeof(bq::Ctrl), s));
+    BQ_HIP_TRY(hipMemsetAsync(q->ctrl, 0, sizeof(bq::Ctrl) * MAX_QSEG, s));
     return BQ_OK;
+}
+
+// log2 of the benchmark's segment count (launch field `segments`, 0 = 1):
+// 1, 2, 4 or 8, each segment at least 64*b slots; -1 if invalid
+static int seg_log(const bq_queue* q, const bqh::Launch& L) {
+    const int S = L.segments > 0 ? L.segments : 1;
+    if (S > (int)MAX_QSEG || (S & (S - 1))) return -1;
+    const int lseg = (int)bqh::log2_exact((unsigned long long)S);
+    if ((unsigned long long)(q->capacity >> lseg) < 64ull * (unsigned long long)L.batch) return -1;
+    return lseg;
 }
 
 bq_status bq_create(uint32_t capacity, uint32_t flags, void* stream, bq_queue** out) {
@@ -256,7 +300,7 @@ bq_status bq_create(uint32_t capacity, uint32_t flags, void* stream, bq_queue** 
     q->capacity = capacity;
     q->logN = bqh::log2_exact(capacity);
     if (hipMalloc(&q->slots, sizeof(unsigned long long) * capacity) != hipSuccess ||
-        hipMalloc(&q->ctrl, sizeof(bq::Ctrl)) != hipSuccess ||
+        hipMalloc(&q->ctrl, sizeof(bq::Ctrl) * MAX_QSEG) != hipSuccess ||
         hipMalloc(&q->scratch, 4096) != hipSuccess) {
         bq_destroy(q);
         return BQ_ENOMEM;
@@ -308,10 +352,14 @@ bq_status bq_counters(bq_queue* q, void* stream, uint64_t* h_head, uint64_t* h_t
     return BQ_OK;
 }
 
+// error words of every segment (the unsegmented queue uses block 0)
 static bq_status check_error_and_reset(bq_queue* q, hipStream_t s) {
-    unsigned long long err = 0;
-    BQ_HIP_TRY(hipMemcpyAsync(&err, &q->ctrl->error.v, 8, hipMemcpyDeviceToHost, s));
+    unsigned long long errs[MAX_QSEG];
+    for (unsigned i = 0; i < MAX_QSEG; ++i)
+        BQ_HIP_TRY(hipMemcpyAsync(&errs[i], &q->ctrl[i].error.v, 8, hipMemcpyDeviceToHost, s));
     BQ_HIP_TRY(hipStreamSynchronize(s));
+    unsigned long long err = 0;
+    for (unsigned i = 0; i < MAX_QSEG; ++i) err |= errs[i];
     if (err != 0ull) {
         queue_zero(q, s);
         BQ_HIP_TRY(hipStreamSynchronize(s));
@@ -322,30 +370,32 @@ static bq_status check_error_and_reset(bq_queue* q, hipStream_t s) {
 
 static bq_status bulk(bq_queue* q, bool enq, const int32_t* vals, int32_t* out, uint64_t n,
                       uint64_t* d_n_ok, unsigned long long* d_stats, const bq_launch* launch,
-                      hipStream_t s, bool reset_count) {
+                      hipStream_t s, bool reset_count, unsigned lseg) {
     bqh::Launch L = bqh::resolve(launch, 4 * bqh::device_cus());
     if (L.wg_size % 64 || L.wg_size > 1024 || L.batch < 1 ||
-        64ull * (unsigned long long)L.batch > q->capacity)
+        64ull * (unsigned long long)L.batch > (unsigned long long)(q->capacity >> lseg))
         return BQ_EINVAL;
     if (reset_count) BQ_HIP_TRY(hipMemsetAsync(d_n_ok, 0, 8, s));
     if (n) {
+        const unsigned long long S = 1ull << lseg;
         const unsigned long long K = 64ull * (unsigned long long)L.batch;
-        const unsigned long long chunks = (n + K - 1) / K;
+        const unsigned long long chunks = S * (((n >> lseg) + K - 1) / K);
         const unsigned long long wpb = (unsigned long long)(L.wg_size / 64);
         unsigned long long g = (chunks + wpb - 1) / wpb;
         if (g > (unsigned long long)L.wg_count) g = (unsigned long long)L.wg_count;
-        if (g < 1) g = 1;
+        g -= g % S;  // every segment gets the same number of workgroups
+        if (g < S) g = S;
         const int bwd = (L.flags & BQ_F_BWD) ? 1 : 0;
         if (enq)
             hipLaunchKernelGGL(k_bulk<true>, dim3((unsigned)g), dim3(L.wg_size), 0, s, q->slots,
                                q->ctrl, q->logN, vals, (int32_t*)nullptr, (unsigned long long)n,
                                (unsigned long long*)d_n_ok, d_stats, L.limit,
-                               (unsigned)L.batch, bwd);
+                               (unsigned)L.batch, bwd, lseg);
         else
             hipLaunchKernelGGL(k_bulk<false>, dim3((unsigned)g), dim3(L.wg_size), 0, s, q->slots,
                                q->ctrl, q->logN, (const int32_t*)nullptr, out,
                                (unsigned long long)n, (unsigned long long*)d_n_ok, d_stats,
-                               L.limit, (unsigned)L.batch, bwd);
+                               L.limit, (unsigned)L.batch, bwd, lseg);
         BQ_HIP_TRY(hipGetLastError());
     }
     return BQ_OK;
@@ -355,7 +405,7 @@ bq_status bq_enqueue(bq_queue* q, const int32_t* d_vals, uint64_t n, uint64_t* d
                      const bq_launch* launch, void* stream) {
     if (!q || !d_n_ok || (n && !d_vals)) return BQ_EINVAL;
     hipStream_t s = bqh::as_stream(stream);
-    bq_status st = bulk(q, true, d_vals, nullptr, n, d_n_ok, nullptr, launch, s, true);
+    bq_status st = bulk(q, true, d_vals, nullptr, n, d_n_ok, nullptr, launch, s, true, 0);
     if (st != BQ_OK) return st;
     return check_error_and_reset(q, s);
 }
@@ -364,7 +414,7 @@ bq_status bq_dequeue(bq_queue* q, int32_t* d_out, uint64_t n, uint64_t* d_n_ok,
                      const bq_launch* launch, void* stream) {
     if (!q || !d_n_ok || (n && !d_out)) return BQ_EINVAL;
     hipStream_t s = bqh::as_stream(stream);
-    bq_status st = bulk(q, false, nullptr, d_out, n, d_n_ok, nullptr, launch, s, true);
+    bq_status st = bulk(q, false, nullptr, d_out, n, d_n_ok, nullptr, launch, s, true, 0);
     if (st != BQ_OK) return st;
     return check_error_and_reset(q, s);
 }
@@ -374,6 +424,8 @@ bq_status bq_bench_enqdeq(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
     if (!q || n_ops < 2 || (n_ops & 1ull) || n_ops / 2 > 0x7fffffffull || !h_enq || !h_deq)
         return BQ_EINVAL;
     hipStream_t s = bqh::as_stream(stream);
+    const int lseg = seg_log(q, bqh::resolve(launch, 0));
+    if (lseg < 0 || (n_ops / 2) % (1ull << lseg)) return BQ_EINVAL;
     bq_status st = queue_zero(q, s);
     if (st != BQ_OK) return st;
     BQ_HIP_TRY(hipMemsetAsync(q->scratch, 0, 128, s));
@@ -384,10 +436,12 @@ bq_status bq_bench_enqdeq(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
     hipEvent_t e2;
     BQ_HIP_TRY(hipEventCreate(&e2));
     BQ_HIP_TRY(hipEventRecord(e0, s));
-    st = bulk(q, true, nullptr, nullptr, half, (uint64_t*)cursor, stats, launch, s, false);
+    st = bulk(q, true, nullptr, nullptr, half, (uint64_t*)cursor, stats, launch, s, false,
+              (unsigned)lseg);
     if (st != BQ_OK) return st;
     BQ_HIP_TRY(hipEventRecord(e1, s));
-    st = bulk(q, false, nullptr, nullptr, half, (uint64_t*)(cursor + 1), stats, launch, s, false);
+    st = bulk(q, false, nullptr, nullptr, half, (uint64_t*)(cursor + 1), stats, launch, s,
+              false, (unsigned)lseg);
     if (st != BQ_OK) return st;
     BQ_HIP_TRY(hipEventRecord(e2, s));
     unsigned long long h[4];
@@ -410,6 +464,9 @@ bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
     bqh::Launch L = bqh::resolve(launch, 0);
     if (L.wg_size % 64 || L.wg_size > 1024) return BQ_EINVAL;
     if (L.batch < 1 || 64ull * (unsigned long long)L.batch > q->capacity) return BQ_EINVAL;
+    const int lseg = seg_log(q, L);
+    if (lseg < 0 || (n_ops / 2) % (1ull << lseg)) return BQ_EINVAL;
+    const int S2 = 2 << lseg;  // each segment needs an enqueuer and a dequeuer workgroup
     // co-resident grid: enqueuers spin on Full until dequeuers run, so all
     // workgroups must be resident together (cooperative launch checks it)
     int per_cu = 0;
@@ -417,8 +474,8 @@ bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
     const int max_grid = per_cu * bqh::device_cus();
     int grid = L.wg_count > 0 ? L.wg_count : max_grid;
     if (grid > max_grid) grid = max_grid;
-    grid &= ~1;
-    if (grid < 2) return BQ_EINVAL;
+    grid -= grid % S2;
+    if (grid < S2) return BQ_EINVAL;
     // start from an empty, zeroed queue (outside the timed region)
     bq_status st = queue_zero(q, s);
     if (st != BQ_OK) return st;
@@ -433,7 +490,8 @@ bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
     unsigned long long lim = L.limit;
     unsigned bb = (unsigned)L.batch;
     int bwd = (L.flags & BQ_F_BWD) ? 1 : 0;
-    void* args[] = {&sl, &ct, &lg, &n_half, &el, &dl, &stats, &lim, &bb, &bwd};
+    unsigned ls = (unsigned)lseg;
+    void* args[] = {&sl, &ct, &lg, &n_half, &el, &dl, &stats, &lim, &bb, &bwd, &ls};
     BQ_HIP_TRY(hipEventRecord(q->ev0, s));
     BQ_HIP_TRY(hipLaunchCooperativeKernel((const void*)k_bench_mixed, dim3(grid), dim3(L.wg_size),
                                           args, 0, s));
@@ -450,7 +508,7 @@ bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
         h_out->deq_empty = h[3];
         h_out->ms = ms;
     }
-    if (h_enq_waves) *h_enq_waves = ((grid + 1) / 2) * (L.wg_size / 64);
+    if (h_enq_waves) *h_enq_waves = (grid / 2) * (L.wg_size / 64);
     return st;
 }
 

@@ -152,6 +152,7 @@ Queue ctx_queue(const sssp_ctx* c) {
     Queue q;
     q.slots = c->slots;
     q.ctrl = c->ctrl;
+    q.sig = c->ctrl;
     q.logN = c->logN;
     q.pad = 0;
     q.N = 1ull << c->logN;

@@ -454,6 +454,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         SolveArgs& a = d.a;
         a.q.slots = b->slots + slot_off;
         a.q.ctrl = b->ctrls + k;
+        a.q.sig = a.q.ctrl;
         a.q.logN = bqh::log2_exact(cap);
         a.q.pad = 0;
         a.q.N = cap;

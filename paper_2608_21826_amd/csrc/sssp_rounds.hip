@@ -474,6 +474,7 @@ bq_status sssp_bf_rounds(sssp_rounds_ctx* c, int32_t n, int64_t m, const int64_t
     RoundArgs a;
     a.q.slots = c->slots;
     a.q.ctrl = c->ctrl;
+    a.q.sig = c->ctrl;
     a.q.logN = c->logN;
     a.q.pad = 0;
     a.q.N = 1ull << c->logN;

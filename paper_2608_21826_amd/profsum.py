@@ -2,8 +2,11 @@
 
     python -m paper_2608_21826_amd.profsum trace <results.db>
     python -m paper_2608_21826_amd.profsum pmc <fetch.db> <write.db> <kernel-substring>
+    python -m paper_2608_21826_amd.profsum counters <db> <kernel-substring> <counter>...
 
 `trace` prints per-kernel call counts and average / min / max durations.
+`counters` prints a kernel's counter values per dispatch and their means, and
+the L2 hit rate when TCC_HIT_sum and TCC_MISS_sum are among them.
 `pmc` prints FETCH_SIZE and WRITE_SIZE per dispatch (KiB, as the counters
 read), scales each by what the same counter reads for the calibration copy
 kernel (k_probe_copy: 1 GiB read and 1 GiB written), and prints HBM bytes per
@@ -88,10 +91,29 @@ def pmc(fetch_db: str, write_db: str, kernel: str) -> str:
     return "\n".join(out)
 
 
+def counters(db: str, kernel: str, names) -> str:
+    """Per-dispatch values and means of counters of one kernel; with
+    TCC_HIT_sum and TCC_MISS_sum also the L2 hit rate."""
+    out = [f"kernel = {kernel}"]
+    means = {}
+    for cname in names:
+        vals = [v for k, v in _counter(db, cname).items() if kernel in k][0]
+        means[cname] = sum(vals) / len(vals)
+        out.append(f"{cname}_per_dispatch = {[round(x) for x in vals]}")
+        out.append(f"{cname}_mean = {means[cname]:.0f}")
+    if "TCC_HIT_sum" in means and "TCC_MISS_sum" in means:
+        h, m = means["TCC_HIT_sum"], means["TCC_MISS_sum"]
+        out.append(f"l2_hit_rate = {h / (h + m):.4f}")
+    out.append(f"kernel_source_hash = {kernel_source_hash()}")
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         print(trace(sys.argv[2]))
     elif sys.argv[1] == "pmc":
         print(pmc(sys.argv[2], sys.argv[3], sys.argv[4]))
+    elif sys.argv[1] == "counters":
+        print(counters(sys.argv[2], sys.argv[3], sys.argv[4:]))
     else:
         raise SystemExit(__doc__)

@@ -139,15 +139,23 @@ def _mixed(cap, n_ops, launch=None):
     history.check_conservation(np.arange(half), dl, np.zeros(0))
     # value i: chunk c = i // K of enqueuer wave c % W, lane (i % K) % 64,
     # that lane's item (c // W) * b + (i % K) // 64. Recode as (producer, seq).
-    W = st["enq_waves"]
+    # Partitioned: the same within segment s = i // P (P = half / S), with
+    # W / S enqueuer waves per segment; a producer stays in its segment.
+    S = max(1, (launch or {}).get("segments", 1))
+    P = half // S
+    W = st["enq_waves"] // S
     K = 64 * b
     i = el.astype(np.int64)
-    c = i // K
-    prod = (c % W) * 64 + (i % K) % 64
-    seq = (c // W) * b + (i % K) // 64
+    seg = i // P
+    r = i - seg * P
+    c = r // K
+    prod = (seg * W + c % W) * 64 + (r % K) % 64
+    seq = (c // W) * b + (r % K) // 64
     history.check_producer_fifo((prod << 20) | seq, 20)
+    # each segment's log slice holds only that segment's values
+    assert np.array_equal(seg, np.arange(half) // P)
     h, t, c = q.counters()
-    history.check_quiescent(h, t, c, cap)
+    history.check_quiescent(h, t, c, cap // S)
     q.close()
     return st
 
@@ -168,6 +176,43 @@ def test_mixed_bwd(b):
     """The BWD policy under the mixed scenario: every operation still
     completes (Full/Empty are retried) and the history checks hold."""
     _mixed(4096, 1 << 20, {"ticket_batch": b, "flags": pkg.BQ_F_BWD})
+
+
+@pytest.mark.parametrize("segments", [2, 8])
+@pytest.mark.parametrize("b", [1, 4])
+def test_mixed_partitioned(segments, b):
+    """The partitioned queue (one Broker Queue per XCD): each segment passes
+    the position rule, conservation and per-producer order on its own."""
+    _mixed(1 << 14, 1 << 20, {"ticket_batch": b, "segments": segments})
+
+
+def test_mixed_partitioned_tiny_segments():
+    """8 segments of 128 slots with b = 2: every segment only one chunk deep."""
+    _mixed(1 << 10, 1 << 18, {"ticket_batch": 2, "segments": 8, "wg_count": 16})
+
+
+def test_partitioned_rejects_bad_segment_counts():
+    q = pkg.Queue(1 << 10)
+    for L in ({"segments": 3}, {"segments": 16}, {"segments": 8, "ticket_batch": 4}):
+        with pytest.raises(pkg.BQError):
+            q.bench_mixed(1 << 12, launch=L)
+    with pytest.raises(pkg.BQError):
+        q.bench_mixed(6 * 8 + 2, launch={"segments": 8})  # n_ops/2 not a multiple of 8
+    q.close()
+
+
+@pytest.mark.parametrize("segments", [1, 8])
+@pytest.mark.parametrize("bwd", [False, True])
+def test_enqdeq_partitioned(segments, bwd):
+    q = pkg.Queue(1 << 16)
+    L = {"ticket_batch": 4, "segments": segments, "flags": pkg.BQ_F_BWD if bwd else 0}
+    e, d = q.bench_enqdeq(1 << 17, launch=L)
+    if bwd:  # single-shot checks may refuse under contention
+        assert e["enq_ok"] <= 1 << 16 and d["deq_ok"] <= e["enq_ok"]
+    else:
+        assert e["enq_ok"] == 1 << 16 and d["deq_ok"] == 1 << 16
+        assert e["enq_full"] == 0 and d["deq_empty"] == 0
+    q.close()
 
 
 @pytest.mark.parametrize("cap,n_ops", [(1 << 16, 1 << 16), (1 << 12, 1 << 16)])
