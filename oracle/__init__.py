@@ -18,6 +18,10 @@ Parts and the passages they follow:
   queue of Section III.A (Alg. 1) is linearizable to.
 - ``history``: checks of concurrent queue histories against that
   specification (see ``oracle/history.py``).
+- ``neg_inf``: minus-infinity marking (vertices a reachable negative cycle
+  reaches), beyond the paper's detection.
+- ``bf_jacobi``: the same rounds as Jacobi rounds on all host cores
+  (``cpu_parallel.c``, OpenMP), a multi-core timing baseline only.
 
 All values are exact integers; INF = INT64_MAX marks unreached vertices.
 """
@@ -37,6 +41,9 @@ _LIBDIR = os.path.join(_HERE, "_build")
 _LIB = os.path.join(_LIBDIR, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
+_PSRC = os.path.join(_HERE, "cpu_parallel.c")
+_PLIB = os.path.join(_LIBDIR, "libcpupar.so")
+_plib = None
 
 
 def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
@@ -49,6 +56,57 @@ def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
                    check=True)
     os.replace(tmp, out)
     return out
+
+
+def build_parallel() -> str:
+    """Compile the multi-core baseline (OpenMP) into its own library."""
+    os.makedirs(_LIBDIR, exist_ok=True)
+    tmp = _PLIB + ".tmp%d" % os.getpid()
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _PSRC],
+                   check=True)
+    os.replace(tmp, _PLIB)
+    return _PLIB
+
+
+def load_parallel():
+    global _plib
+    if _plib is not None:
+        return _plib
+    with _lock:
+        if not os.path.exists(_PLIB):
+            build_parallel()
+        lib = ctypes.CDLL(_PLIB)
+        i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+        lib.cpu_transpose.restype = None
+        lib.cpu_transpose.argtypes = [i32, vp, vp, vp, vp, vp, vp]
+        lib.cpu_bf_jacobi.restype = i64
+        lib.cpu_bf_jacobi.argtypes = [i32, vp, vp, vp, i32, vp, vp, vp]
+        _plib = lib
+        return lib
+
+
+def transpose(g):
+    """CSC of g: (toff int64[n+1], tsrc int32[m], tw int32[m])."""
+    lib = load_parallel()
+    off, col, w = _csr(g)
+    toff = np.empty(g.n + 1, dtype=np.int64)
+    tsrc = np.empty(col.shape[0], dtype=np.int32)
+    tw = np.empty(col.shape[0], dtype=np.int32)
+    lib.cpu_transpose(g.n, _ptr(off), _ptr(col), _ptr(w), _ptr(toff), _ptr(tsrc), _ptr(tw))
+    return toff, tsrc, tw
+
+
+def bf_jacobi(g, csc, src: int | None = None):
+    """Jacobi rounds on all OpenMP threads over the transposed graph.
+    Returns (dist, neg, rounds, threads)."""
+    lib = load_parallel()
+    toff, tsrc, tw = csc
+    s = g.src if src is None else int(src)
+    d = np.empty(g.n, dtype=np.int64)
+    neg = np.zeros(1, dtype=np.int32)
+    thr = np.zeros(1, dtype=np.int32)
+    r = lib.cpu_bf_jacobi(g.n, _ptr(toff), _ptr(tsrc), _ptr(tw), s, _ptr(d), _ptr(neg), _ptr(thr))
+    return d, bool(neg[0]), int(r), int(thr[0])
 
 
 def load(path: str | None = None):

@@ -76,38 +76,12 @@ __global__ void k_reset(bq::Ctrl* c) {
     for (int i = 0; i < bq::ST_N; ++i) c->stats[i].v = 0ull;
 }
 
-// Distances (d[src] = 0, otherwise infinity), the edge-source array and the
-// largest |w|. One wave per group of 64 consecutive vertices writes the
-// sources of the group's edges: lane l holds offsets[v0 + l], and each edge
-// finds its row by a binary search over the wave's 64 offsets.
-__global__ __launch_bounds__(PREP_WG) void k_prep(const long long* off, const int* w, int n,
-                                                  long long m, int src, long long* dist,
-                                                  int* esrc, bq::Ctrl* ctrl) {
+// Distances (d[src] = 0, otherwise infinity) and the largest |w|.
+__global__ __launch_bounds__(PREP_WG) void k_prep(const int* w, int n, long long m, int src,
+                                                  long long* dist, bq::Ctrl* ctrl) {
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long v = tid; v < n; v += stride) dist[v] = v == src ? 0ll : DINF;
-
-    const int lane = bq::lane_id();
-    const long long wave = tid >> 6, waves = stride >> 6;
-    const long long groups = ((long long)n + 63) >> 6;
-    for (long long g = wave; g < groups; g += waves) {
-        const long long v0 = g << 6;
-        const long long vl = v0 + lane;
-        const long long v1 = v0 + 64 < n ? v0 + 64 : n;
-        const long long e0 = off[v0], e1 = off[v1];
-        const long long mine = vl < v1 ? off[vl] : e1;  // rows past n never match
-        for (long long e = e0 + lane; __any(e < e1); e += 64) {
-            // largest l with offsets[v0 + l] <= e
-            int lo = 0;
-#pragma unroll
-            for (int step = 32; step > 0; step >>= 1) {
-                const long long o = __shfl(mine, lo + step, 64);
-                if (lo + step < 64 && o <= e) lo += step;
-            }
-            if (e < e1) esrc[e] = (int)(v0 + lo);
-        }
-    }
-
     unsigned long long wmax = 0;
     for (long long e = tid; e < m; e += stride) {
         const long long x = w[e];
@@ -118,9 +92,69 @@ __global__ __launch_bounds__(PREP_WG) void k_prep(const long long* off, const in
         const unsigned long long y = __shfl_xor(wmax, o, 64);
         wmax = y > wmax ? y : wmax;
     }
-    if (lane == 0 && wmax)
+    if (bq::lane_id() == 0 && wmax)
         __hip_atomic_fetch_max(&ctrl->aux[A_WMAX].v, wmax, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Edge-source array esrc[e] = the row holding edge e. Waves take ranges of
+// SRC_RANGE edges, so a hub row is shared out like any other edges. A range
+// starts in the row found by a binary search over the offsets. In each step
+// of 64 edges the lanes hold the ends of the next 64 rows (as 32-bit
+// distances from the range start) and every lane finds its row by a binary
+// search over them; the window slides by 64 rows while some edge lies
+// beyond it (runs of empty rows).
+constexpr long long SRC_RANGE = 4096;
+
+__global__ __launch_bounds__(PREP_WG) void k_edge_src(const long long* off, int n, long long m,
+                                                      int* esrc) {
+    const int lane = bq::lane_id();
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long waves = ((long long)gridDim.x * blockDim.x) >> 6;
+    for (long long E = wave * SRC_RANGE; E < m; E += waves * SRC_RANGE) {
+        const long long Eend = E + SRC_RANGE < m ? E + SRC_RANGE : m;
+        // largest r with off[r] <= E (off[0] = 0 <= E < m = off[n])
+        long long r = 0;
+        if (lane == 0) {
+            long long lo = 0, hi = n;
+            while (hi - lo > 1) {
+                const long long mid = (lo + hi) >> 1;
+                if (off[mid] <= E) lo = mid;
+                else hi = mid;
+            }
+            r = lo;
+        }
+        r = (long long)bq::bcast64((unsigned long long)r);
+        for (long long e0 = E; e0 < Eend; e0 += 64) {
+            const long long e = e0 + lane;
+            const bool act = e < Eend;
+            const int x = (int)(e - E);
+            long long row = -1;
+            bool todo = act;
+            while (__any(todo)) {
+                const long long j = r + 1 + lane;
+                const long long d = (j <= n ? off[j] : LLONG_MAX) - E;
+                const int rel = d > INT_MAX ? INT_MAX : (int)d;
+                // rows r .. r+cnt-1 end at or before e: e lies in row r+cnt
+                int cnt = 0;
+#pragma unroll
+                for (int step = 32; step > 0; step >>= 1) {
+                    const int v = __shfl(rel, cnt + step - 1, 64);
+                    if (v <= x) cnt += step;
+                }
+                if (__shfl(rel, 63, 64) <= x) cnt = 64;  // past this window
+                if (todo && cnt < 64) {
+                    row = r + cnt;
+                    todo = false;
+                }
+                if (__any(todo)) r += 64;
+            }
+            if (act) esrc[e] = (int)row;
+            // the next step starts in the row of this step's last edge
+            const int last = (int)((Eend - e0 < 64 ? Eend - e0 : 64) - 1);
+            r = __shfl(row, last, 64);
+        }
+    }
 }
 
 // One round: enqueue every edge id (grid-stride chunks of `items`), then
@@ -494,9 +528,18 @@ bq_status sssp_bf_rounds(sssp_rounds_ctx* c, int32_t n, int64_t m, const int64_t
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, c->ctrl);
     BQ_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_prep, dim3(grid_for(m > n ? m : n)), dim3(PREP_WG), 0, s,
-                       (const long long*)d_offsets, (const int*)d_w, n, (long long)m, src,
-                       (long long*)d_dist, c->esrc, c->ctrl);
+                       (const int*)d_w, n, (long long)m, src, (long long*)d_dist, c->ctrl);
     BQ_HIP_TRY(hipGetLastError());
+    if (m > 0) {
+        // one wave per range of SRC_RANGE edges, 4 waves per workgroup
+        const long long ranges = ((long long)m + SRC_RANGE - 1) / SRC_RANGE;
+        const long long cap = 8ll * bqh::device_cus();
+        long long blocks = (ranges + 3) / 4;
+        if (blocks > cap) blocks = cap;
+        hipLaunchKernelGGL(k_edge_src, dim3((unsigned)blocks), dim3(PREP_WG), 0, s,
+                           (const long long*)d_offsets, n, (long long)m, c->esrc);
+        BQ_HIP_TRY(hipGetLastError());
+    }
     BQ_HIP_TRY(hipEventRecord(c->evs0, s));
     const double t0 = host_seconds();
     long long round = 0, group = 4;

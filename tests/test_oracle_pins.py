@@ -531,3 +531,27 @@ def test_neg_inf_long_path_then_cycle():
     assert np.all(d[50:55] == oracle.NEG_INF)
     assert np.all(d[55:] == INF)
     assert np.all(p[50:] == -1)
+
+
+# ---------------------------------------------------------------------------
+# the multi-core timing baseline gives the oracle's results
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(60))
+def test_jacobi_baseline_matches_rounds(seed):
+    rng = np.random.default_rng(30000 + seed)
+    n = int(rng.integers(1, 80))
+    g = synth.random_small(n, int(rng.integers(0, 5 * n + 1)), -6, 30, seed=31000 + seed)
+    src = int(rng.integers(0, n))
+    d, neg, rounds, threads = oracle.bf_jacobi(g, oracle.transpose(g), src)
+    d_ref, neg_ref, _ = oracle.bf_rounds(g, src)
+    assert neg == neg_ref and threads >= 1
+    if not neg:
+        assert np.array_equal(d, d_ref)
+
+
+def test_jacobi_baseline_medium():
+    g = synth.rmat(14, 16, seed=5)
+    d, neg, rounds, threads = oracle.bf_jacobi(g, oracle.transpose(g))
+    d_ref, neg_ref, _ = oracle.bf_rounds(g)
+    assert not neg and not neg_ref and np.array_equal(d, d_ref)
