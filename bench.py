@@ -498,7 +498,7 @@ def main():
     if args.sssp_launch:
         sssp_launch = json.loads(args.sssp_launch)
     elif not args.no_tune:
-        sssp_launch, tune_ms = ctx.autotune(off, col, w, g.src, reps=2)
+        sssp_launch, tune_ms = ctx.autotune(off, col, w, g.src, reps=5)
         log(f"sssp autotune: {sssp_launch} {tune_ms:.3f} ms")
     queue_launch = {"ticket_batch": 1}
     queue_b1_ms = None

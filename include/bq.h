@@ -262,10 +262,12 @@ bq_status sssp_bf(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
 
 /* Autotuner: time sssp_bf on this input (d_dist is used as scratch) for
  * workgroup counts 4, 8, 16, ... up to the co-resident maximum (stopping
- * once clearly past the fastest), then ticket batches b = 2, 4 around the
+ * once clearly past the fastest) and 3/4 and 3/2 of the fastest, then
+ * ticket batches b = 2, 4 around the
  * fastest count, then row chunks 256 and 4096 at the fastest shape, then
  * 1, 2 and 4 queue segments against the default; `reps` runs per candidate
- * (the fastest counts).
+ * (0 = 5), compared by their median, a candidate replacing the fastest so
+ * far only when at least 3 % faster.
  * *h_best gets the fastest launch (other fields copied from `base`, which
  * may be NULL), *h_best_ms its time. Synchronous. */
 bq_status sssp_autotune(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,

@@ -343,7 +343,7 @@ class SsspContext:
                              _stream(stream)), "sssp_bf")
         return dist, pred, bool(neg.value)
 
-    def autotune(self, offsets, cols, w, src: int, reps: int = 2, base=None, stream=None):
+    def autotune(self, offsets, cols, w, src: int, reps: int = 5, base=None, stream=None):
         """sssp_autotune: returns (launch dict, best ms)."""
         import torch
         n = offsets.numel() - 1

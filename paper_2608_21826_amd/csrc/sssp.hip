@@ -1,114 +1,18 @@
-// Single-query launch of the queue-based Bellman-Ford SSSP (Section III.C)
-// and its host API: init, persistent solver, unpack, autotuner.
+// Host API of the single-query queue-based Bellman-Ford SSSP (Section III.C):
+// context, launch sequence (init, persistent solver, unpack; kernels in
+// sssp_kernels.hpp), autotuner.
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "csr_device.hpp"
 #include "host_common.hpp"
-#include "sssp_device.hpp"
+#include "sssp_kernels.hpp"
 
-namespace {
-
-// ---------------------------------------------------------------------------
-// init: keys, the per-block weight range, and (block 0) the control block
-// with the source already enqueued
-// ---------------------------------------------------------------------------
-constexpr int INIT_WG = 256;
-constexpr int INIT_MAX_BLOCKS = 1024;
-
-__global__ __launch_bounds__(INIT_WG) void k_init(Queue q, long long* key, int n, int src,
-                                                  unsigned shift, const int* w, long long m,
-                                                  int* wrange /* [2 * gridDim.x] */) {
-    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    const long long srckey = pack_key(0, (1u << (shift - 1u)) - 1u, shift);
-    for (long long v = tid; v < n; v += stride) key[v] = (v == src) ? srckey : KEY_INF;
-    int lo = INT_MAX, hi = INT_MIN;
-    for (long long e = tid; e < m; e += stride) {
-        const int x = w[e];
-        lo = x < lo ? x : lo;
-        hi = x > hi ? x : hi;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        const int a2 = __shfl_xor(lo, off, 64), b2 = __shfl_xor(hi, off, 64);
-        lo = a2 < lo ? a2 : lo;
-        hi = b2 > hi ? b2 : hi;
-    }
-    __shared__ int slo[INIT_WG / 64], shi[INIT_WG / 64];
-    if (bq::lane_id() == 0) {
-        slo[threadIdx.x >> 6] = lo;
-        shi[threadIdx.x >> 6] = hi;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < INIT_WG / 64; ++i) {
-            lo = slo[i] < lo ? slo[i] : lo;
-            hi = shi[i] > hi ? shi[i] : hi;
-        }
-        wrange[2 * blockIdx.x] = lo;
-        wrange[2 * blockIdx.x + 1] = hi;
-    }
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    bq::Ctrl* c = q.ctrl;
-    c->pending.v = 1ull;
-    c->abort.v = 0ull;
-    c->error.v = 0ull;
-    c->negcycle.v = 0ull;
-    c->aux[0].v = (unsigned long long)gridDim.x;  // number of weight-range partials
-    for (unsigned sg = 0; sg < MAX_SEG; ++sg)      // dequeue positions at start
-        q.ctrl[sg].aux[2].v = q.ctrl[sg].head.v;
-    c->aux[4].v = bq::now_ticks();                // clock at start
-    for (int i = 0; i < bq::ST_N; ++i) c->stats[i].v = 0ull;
-    // enqueue src: the queue is quiescent, so slot (tail mod N) is free for
-    // this round (ticket 2r) and count is 0
-    const unsigned long long pos = c->tail.v;
-    const unsigned slot = (unsigned)(pos & (q.N - 1ull));
-    const unsigned round = (unsigned)(pos >> q.logN);
-    q.slots[slot] = bq::slot_word(2u * round + 1u, (unsigned)src);
-    c->tail.v = pos + 1ull;
-    c->count.v = 1ull;
-}
-
-template <int B>
-__global__ __launch_bounds__(SOLVE_WG, SSSP_MIN_WAVES) void k_solve(SolveArgs a) {
-    __shared__ WaveLds<B> lds[WAVES_PER_WG];
-    __shared__ WgShared S;
-    WaveLds<B>& L = lds[threadIdx.x >> 6];
-    const int wid = (int)(threadIdx.x >> 6);
-    if (threadIdx.x == 0) {
-        S.poller = -1;
-        S.wake = 0u;
-        S.done = 0;
-    }
-    __syncthreads();
-    WaveStats st{};
-    solve_instance<B>(a, L, S, wid, st);
-    flush_stats(a.q.ctrl->stats, st);
-}
-
-// dist[v] = d, pred[v] = parent (INT64_MAX / -1 when unreached; pred[src] = -1;
-// INT64_MIN / -1 for minus infinity)
-__global__ void k_unpack(long long* key, int* pred, int n, int src, unsigned shift) {
-    const long long dmax = KEY_INF >> shift;
-    const unsigned pmask = (1u << (shift - 1u)) - 1u;
-    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (long long)gridDim.x * blockDim.x) {
-        const long long k = key[v];
-        if (is_neg_key(k)) {  // minus infinity (marking mode)
-            key[v] = LLONG_MIN;
-            if (pred) pred[v] = -1;
-            continue;
-        }
-        const long long d = k >> shift;
-        const bool reached = d != dmax;
-        key[v] = reached ? d : LLONG_MAX;
-        if (pred) pred[v] = (reached && v != src) ? (int)(((unsigned long long)k >> 1) & pmask) : -1;
-    }
-}
-
-}  // namespace
 
 // ---------------------------------------------------------------------------
 // host API
@@ -289,7 +193,7 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
                         const bq_launch* base, int32_t reps, bq_launch* h_best,
                         double* h_best_ms, void* stream) {
     if (!c || !h_best || !h_best_ms || !d_dist) return BQ_EINVAL;
-    if (reps < 1) reps = 2;
+    if (reps < 1) reps = 5;
     bq_launch L = {};
     if (base) L = *base;
     L.flags &= ~(uint32_t)(BQ_F_TRACE | BQ_F_VALIDATE);
@@ -306,17 +210,23 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
         t.ticket_batch = b;
         if (chunk >= 0) t.row_chunk = chunk;
         if (seg >= 0) t.segments = seg;
-        double tmin = 1e300;
+        // the median of the runs: the work of an asynchronous solve varies
+        // from run to run, and a lucky minimum would pick a shape that is
+        // slower on average
+        std::vector<double> ts;
         for (int r = 0; r < reps; ++r) {
             int32_t neg = 0;
             bq_status st = sssp_bf(c, n, m, d_offsets, d_cols, d_w, src, d_dist, nullptr, &neg,
                                    &t, stream);
             if (st != BQ_OK) return st;
-            if (c->last.ms < tmin) tmin = c->last.ms;
+            ts.push_back(c->last.ms);
         }
-        *out_ms = tmin;
-        if (tmin < best) {
-            best = tmin;
+        std::sort(ts.begin(), ts.end());
+        const double med = (ts[(ts.size() - 1) / 2] + ts[ts.size() / 2]) / 2.0;
+        *out_ms = med;
+        // a new shape must beat the incumbent by 3 % to replace it
+        if (med < best * (best < 1e300 ? 0.97 : 1.0)) {
+            best = med;
             bestL = t;
         }
         return BQ_OK;
@@ -327,13 +237,21 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
         double ms = 0;
         bq_status st = trial(wgs, 1, &ms);
         if (st != BQ_OK) return st;
-        if (ms <= best) best_wgs = wgs;
+        if (bestL.wg_count == wgs) best_wgs = wgs;
         if (ms > 2.0 * best && wgs >= 4 * best_wgs) break;
         if (wgs * 2 > max_grid && wgs != max_grid) {
             st = trial(max_grid, 1, &ms);
             if (st != BQ_OK) return st;
         }
     }
+    // counts between the powers of two around the best
+    for (int wgs : {best_wgs * 3 / 4, best_wgs * 3 / 2}) {
+        if (wgs < 1 || wgs > max_grid || wgs == best_wgs) continue;
+        double ms = 0;
+        bq_status st = trial(wgs, 1, &ms);
+        if (st != BQ_OK) return st;
+    }
+    best_wgs = bestL.wg_count;
     // ticket batch at the best count and its neighbours
     for (int b = 2; b <= 4; b *= 2) {
         for (int f = -1; f <= 1; ++f) {

@@ -25,7 +25,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CALIB_BYTES = 1 << 30
 
 
-KERNEL_SOURCES = ("bq_device.hpp", "sssp_device.hpp", "sssp.hip")
+KERNEL_SOURCES = ("bq_device.hpp", "sssp_device.hpp", "sssp_kernels.hpp")
 
 
 def kernel_source_hash() -> str:
