@@ -144,6 +144,25 @@ def cpu_baselines_more(g, m_reached, budget_s=5.0):
     return out
 
 
+def cpu_queue_baselines(threads=None):
+    """The queue on the host (bounded samples): a sequential ring on one core
+    running the Global Mixed sequence (2^26 operations), and Alg. 1's Broker
+    Queue with C11 atomics on all host threads (2^22 operations, 2^20 slots)."""
+    import oracle
+    threads = threads or max(2, (os.cpu_count() or 2))
+    threads = int(os.environ.get("OMP_NUM_THREADS", threads))
+    t_ring = min(oracle.ring_mixed(QUEUE_CAP, QUEUE_OPS) for _ in range(2))
+    n = 1 << 22
+    t_bq, fails, _, _ = oracle.bq_mixed(QUEUE_CAP, n, threads)
+    return {"ring_1core": {"value": round(QUEUE_OPS / t_ring / 1e6, 1), "unit": "Mops/s",
+                           "cores": 1, "kind": "sequential_ring",
+                           "sample": "2^26 operations alternating enqueue / dequeue"},
+            "bq_model_all_threads": {"value": round(n / t_bq / 1e6, 2), "unit": "Mops/s",
+                                     "cores": threads, "kind": "broker_queue_cpu_model",
+                                     "sample": f"2^22 operations (Global Mixed), 2^20 slots, "
+                                               f"{fails} Full/Empty retries"}}
+
+
 def run_probes(pkg, torch, dev):
     """Measured peaks of the resources the solver uses (context for the
     roofline; the reported peak stays the published HBM figure)."""
@@ -645,6 +664,7 @@ def main():
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(g, m_reached)
         out["cpu_baselines_more"] = cpu_baselines_more(g, m_reached)
+        out["cpu_queue_baselines"] = cpu_queue_baselines()
     print(json.dumps(out), flush=True)
 
 

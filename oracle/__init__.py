@@ -22,6 +22,9 @@ Parts and the passages they follow:
   reaches), beyond the paper's detection.
 - ``bf_jacobi``: the same rounds as Jacobi rounds on all host cores
   (``cpu_parallel.c``, OpenMP), a multi-core timing baseline only.
+- ``ring_mixed`` / ``bq_mixed``: the queue's CPU baselines (``queue_cpu.c``):
+  a sequential ring on one core, and Alg. 1's Broker Queue with C11 atomics
+  on host threads (checked with the same history checks as the GPU queue).
 
 All values are exact integers; INF = INT64_MAX marks unreached vertices.
 """
@@ -41,7 +44,7 @@ _LIBDIR = os.path.join(_HERE, "_build")
 _LIB = os.path.join(_LIBDIR, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
-_PSRC = os.path.join(_HERE, "cpu_parallel.c")
+_PSRC = [os.path.join(_HERE, "cpu_parallel.c"), os.path.join(_HERE, "queue_cpu.c")]
 _PLIB = os.path.join(_LIBDIR, "libcpupar.so")
 _plib = None
 
@@ -62,8 +65,8 @@ def build_parallel() -> str:
     """Compile the multi-core baseline (OpenMP) into its own library."""
     os.makedirs(_LIBDIR, exist_ok=True)
     tmp = _PLIB + ".tmp%d" % os.getpid()
-    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _PSRC],
-                   check=True)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-pthread", "-shared", "-fPIC",
+                    "-D_GNU_SOURCE", "-o", tmp] + _PSRC, check=True)
     os.replace(tmp, _PLIB)
     return _PLIB
 
@@ -81,6 +84,11 @@ def load_parallel():
         lib.cpu_transpose.argtypes = [i32, vp, vp, vp, vp, vp, vp]
         lib.cpu_bf_jacobi.restype = i64
         lib.cpu_bf_jacobi.argtypes = [i32, vp, vp, vp, i32, vp, vp, vp]
+        f64 = ctypes.c_double
+        lib.cpu_ring_mixed.restype = f64
+        lib.cpu_ring_mixed.argtypes = [i64, i64, vp]
+        lib.cpu_bq_mixed.restype = f64
+        lib.cpu_bq_mixed.argtypes = [i64, i64, i32, vp, vp, vp]
         _plib = lib
         return lib
 
@@ -107,6 +115,26 @@ def bf_jacobi(g, csc, src: int | None = None):
     thr = np.zeros(1, dtype=np.int32)
     r = lib.cpu_bf_jacobi(g.n, _ptr(toff), _ptr(tsrc), _ptr(tw), s, _ptr(d), _ptr(neg), _ptr(thr))
     return d, bool(neg[0]), int(r), int(thr[0])
+
+
+def ring_mixed(capacity: int, n_ops: int):
+    """Sequential ring, alternating enqueue / dequeue: returns seconds."""
+    chk = np.zeros(1, dtype=np.int64)
+    return float(load_parallel().cpu_ring_mixed(capacity, n_ops, _ptr(chk)))
+
+
+def bq_mixed(capacity: int, n_ops: int, threads: int, log: bool = False):
+    """Alg. 1's Broker Queue on host threads, Global Mixed: returns
+    (seconds, Full/Empty retries, enq_log, deq_log) (logs None unless asked)."""
+    el = dl = None
+    if log:
+        el = np.full(n_ops // 2, -1, dtype=np.int32)
+        dl = np.full(n_ops // 2, -1, dtype=np.int32)
+    fails = np.zeros(1, dtype=np.int64)
+    t = load_parallel().cpu_bq_mixed(capacity, n_ops, threads,
+                                     _ptr(el) if log else None, _ptr(dl) if log else None,
+                                     _ptr(fails))
+    return float(t), int(fails[0]), el, dl
 
 
 def load(path: str | None = None):
