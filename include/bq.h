@@ -267,7 +267,10 @@ bq_status sssp_bf(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
  * fastest count, then row chunks 256 and 4096 at the fastest shape, then
  * 1, 2 and 4 queue segments against the default; `reps` runs per candidate
  * (0 = 5), compared by their median, a candidate replacing the fastest so
- * far only when at least 3 % faster.
+ * far only when at least 3 % faster; a winner with another ticket batch, row
+ * chunk or segment count is finally run against the plain shape (best
+ * count, b = 1), 2 * reps times each, alternating, and kept only if its
+ * median is lower.
  * *h_best gets the fastest launch (other fields copied from `base`, which
  * may be NULL), *h_best_ms its time. Synchronous. */
 bq_status sssp_autotune(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
@@ -361,7 +364,9 @@ bq_status sssp_batch_destroy(sssp_batch* b);
  * pred, h_neg_cycle[i]). Queries are ordered by size; persistent workgroups
  * claim them biggest first, each query getting workgroups in proportion to
  * its edges + vertices, and workgroups whose claims are used up join
- * unfinished queries. With BQ_F_GRAPH the init / solve / unpack kernels run
+ * unfinished queries. A query with (n + m/16) / 16384 >= 16 gets up to 8
+ * queue segments (as sssp_bf) while the workspace's slots allow, biggest
+ * first. With BQ_F_GRAPH the init / solve / unpack kernels run
  * as one replayed hipGraph on the batch's own stream (ordered after the
  * caller's stream). Synchronous. Errors: BQ_EINVAL (a bad query), BQ_EBUSY
  * (batch larger than the workspace), BQ_ERANGE / BQ_ETIMEOUT (first failing
@@ -384,8 +389,13 @@ bq_status sssp_batch_finish(sssp_batch* b, int32_t* h_neg_cycle, int64_t* h_reac
 bq_status sssp_batch_last_stats(const sssp_batch* b, sssp_stats* h_out);
 
 /* Autotuner for a batch: workgroup counts 16, 32, ... up to the co-resident
- * maximum, then row chunks 256 / 4096, ticket batch 2 and queue_scale 1 at
- * the fastest shape; returns the fastest launch and its time. */
+ * maximum, then row chunks 256 / 4096, ticket batches 2 and 4 and
+ * queue_scale 1 at the fastest shape; `reps` runs per candidate (0 = 3)
+ * compared by their median, a candidate replacing the fastest so far only
+ * when at least 3 % faster. Returns the fastest launch and its time. The
+ * result is kept per shape bucket (powers of two of the query count, total
+ * vertices and total edges, and base->flags): a later call on the same
+ * batch workspace with a batch of the same bucket returns it at once. */
 bq_status sssp_batch_autotune(sssp_batch* b, int32_t count, const sssp_instance* h_inst,
                               const bq_launch* base, int32_t reps, bq_launch* h_best,
                               double* h_best_ms, void* stream);

@@ -12,7 +12,9 @@
 //   arrived and fit (in arrival order, up to the lane's batch limits) and
 //   starts one batched launch for them; requests that arrive while other
 //   launches run are picked up by the next free lane, so their work overlaps
-//   on the device.
+//   on the device. Large requests (enough work for 64 or more workgroups)
+//   go alone, so they run with all queue segments and small requests are
+//   not held back until a large one in their batch finishes.
 // - Latency = arrival (trace time) to the moment the engine sees the launch
 //   complete; the loop runs on the calling thread with a steady clock.
 #include <hip/hip_runtime.h>
@@ -28,6 +30,9 @@
 #include <vector>
 
 #include "host_common.hpp"
+
+// a request with work for this many workgroups ((n + m/16) / 16K) is large
+constexpr long long LARGE_WGS = 64;
 
 // ---------------------------------------------------------------------------
 // first-fit arena over offsets (pure host logic)
@@ -316,9 +321,20 @@ bq_status bq_server_run(bq_server* s, int32_t count, const bq_request* reqs,
             L.reqs.clear();
             L.blocks.clear();
             int64_t sn = 0, sm = 0;
-            while (!pending.empty() && (int)L.reqs.size() < s->max_batch) {
-                const int i = pending.front();
+            // size classes: a large request (one that can feed LARGE_WGS or
+            // more workgroups on its own) is launched alone, so it runs with the
+            // whole queue-segment set and small requests do not wait for it;
+            // small requests are batched together in arrival order, passing
+            // over large ones, which keep their place at the front
+            std::size_t scan = 0;
+            while (scan < pending.size() && (int)L.reqs.size() < s->max_batch) {
+                const int i = pending[scan];
                 const Need& nd = need[i];
+                const bool large = ((long long)nd.n + nd.m / 16) / 16384 >= LARGE_WGS;
+                if (large && !L.reqs.empty()) {
+                    ++scan;
+                    continue;
+                }
                 if (sn + nd.n > s->max_batch_n || sm + nd.m > s->max_batch_m) break;
                 // admission by footprint: uploads and engine-owned outputs
                 uint64_t off_up = 0, off_out = 0;
@@ -333,7 +349,7 @@ bq_status bq_server_run(bq_server* s, int32_t count, const bq_request* reqs,
                     ok = false;
                 }
                 if (!ok) break;  // arrival order is kept: wait for memory to free up
-                pending.pop_front();
+                pending.erase(pending.begin() + (std::ptrdiff_t)scan);
                 sssp_instance q{};
                 q.n = nd.n;
                 q.m = nd.m;
@@ -375,6 +391,7 @@ bq_status bq_server_run(bq_server* s, int32_t count, const bq_request* reqs,
                 inst.push_back(q);
                 L.reqs.push_back(i);
                 resp[i].wait_us = now_us() - r.arrival_us;
+                if (large) break;
             }
             if (inst.empty()) continue;
             L.neg.assign(inst.size(), 0);

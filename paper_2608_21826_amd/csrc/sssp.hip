@@ -282,6 +282,35 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
             if (st != BQ_OK) return st;
         }
     }
+    // confirmation: the winner against the plain shape (the best count at
+    // b = 1 with the caller's other fields), alternating runs, so that one
+    // lucky series cannot pick a shape that is slower on average
+    if (bestL.ticket_batch != 1 || bestL.row_chunk != L.row_chunk ||
+        bestL.segments != L.segments) {
+        bq_launch plain = L;
+        plain.wg_count = best_wgs;
+        plain.ticket_batch = 1;
+        std::vector<double> ta, tb;
+        for (int r = 0; r < 2 * reps; ++r) {
+            for (int side = 0; side < 2; ++side) {
+                int32_t neg = 0;
+                bq_launch t = side ? plain : bestL;
+                bq_status st = sssp_bf(c, n, m, d_offsets, d_cols, d_w, src, d_dist, nullptr,
+                                       &neg, &t, stream);
+                if (st != BQ_OK) return st;
+                (side ? tb : ta).push_back(c->last.ms);
+            }
+        }
+        std::sort(ta.begin(), ta.end());
+        std::sort(tb.begin(), tb.end());
+        const double ma = ta[ta.size() / 2], mb = tb[tb.size() / 2];
+        if (mb <= ma) {
+            bestL = plain;
+            best = mb;
+        } else {
+            best = ma;
+        }
+    }
     *h_best = bestL;
     *h_best_ms = best;
     return BQ_OK;

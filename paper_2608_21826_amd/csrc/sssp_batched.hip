@@ -20,6 +20,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "host_common.hpp"
@@ -99,7 +101,8 @@ __global__ __launch_bounds__(BINIT_WG) void k_binit(const InstDesc* D, const Uni
                 c->error.v = 0ull;
                 c->negcycle.v = 0ull;
                 c->aux[0].v = (unsigned long long)(d.unit_end - d.unit_begin);
-                c->aux[2].v = c->head.v;
+                for (unsigned sg = 0; sg < a.nseg; ++sg)  // dequeue positions at start
+                    c[sg].aux[2].v = c[sg].head.v;
                 c->aux[4].v = bq::now_ticks();
                 c->aux[5].v = 0ull;  // finished flag
                 for (int i = 0; i < bq::ST_N; ++i) c->stats[i].v = 0ull;
@@ -237,6 +240,8 @@ struct sssp_batch {
     hipEvent_t ev0, ev1, ev_in, ev_done;
     std::vector<unsigned long long> layout;
     bool dirty;
+    // autotuned launches by shape bucket (sssp_batch_autotune)
+    std::map<unsigned long long, std::pair<bq_launch, double>> tuned;
     hipGraphExec_t exec;
     hipGraph_t graph;
     unsigned long long graph_key[8];
@@ -310,7 +315,7 @@ bq_status sssp_batch_create(int32_t max_instances, int64_t max_total_n, int64_t 
     b->max_claim = (size_t)(8 * 4096 + max_instances);
     if (hipMalloc(&b->slots, sizeof(unsigned long long) * b->slot_cap) != hipSuccess ||
         hipMalloc(&b->chunks, sizeof(unsigned) * b->chunk_cap) != hipSuccess ||
-        hipMalloc(&b->ctrls, sizeof(bq::Ctrl) * max_instances) != hipSuccess ||
+        hipMalloc(&b->ctrls, sizeof(bq::Ctrl) * max_instances * MAX_SEG) != hipSuccess ||
         hipMalloc(&b->d_desc, sizeof(InstDesc) * max_instances) != hipSuccess ||
         hipMalloc(&b->d_units, sizeof(Unit) * b->max_units) != hipSuccess ||
         hipMalloc(&b->d_claim, sizeof(int) * b->max_claim) != hipSuccess ||
@@ -339,7 +344,8 @@ bq_status sssp_batch_create(int32_t max_instances, int64_t max_total_n, int64_t 
     BQ_HIP_TRY(hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
     b->dirty = true;
     BQ_HIP_TRY(hipMemsetAsync(b->slots, 0, sizeof(unsigned long long) * b->slot_cap, b->stream));
-    BQ_HIP_TRY(hipMemsetAsync(b->ctrls, 0, sizeof(bq::Ctrl) * max_instances, b->stream));
+    BQ_HIP_TRY(hipMemsetAsync(b->ctrls, 0, sizeof(bq::Ctrl) * max_instances * MAX_SEG,
+                              b->stream));
     BQ_HIP_TRY(hipStreamSynchronize(b->stream));
     b->dirty = false;
     *out = b;
@@ -431,29 +437,55 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
 
     // layout: queue slots, chunk tables, units, claim list
     std::vector<unsigned long long> layout;
-    layout.reserve(2 * count + 2);
+    layout.reserve(3 * count + 2);
     size_t slot_off = 0, chunk_off = 0;
     int n_units = 0, n_claim = 0;
     long long tot_work = 0;
     for (int i = 0; i < count; ++i) tot_work += work[i];
+    // queue capacity of each query, and its segments: a query that can feed
+    // 16 or more workgroups gets up to MAX_SEG queue segments (one per XCD,
+    // as in the single-query solver) while the slot arena has room left over
+    // after every query's first segment, biggest queries first
+    std::vector<unsigned long long> caps(count);
+    std::vector<unsigned> nsegs(count, 1u);
+    {
+        unsigned long long base = 0;
+        for (int k = 0; k < count; ++k) {
+            const sssp_instance& x = h_inst[order[k]];
+            const unsigned long long need =
+                (unsigned long long)x.n + ((unsigned long long)x.m >> clog) + 1ull;
+            unsigned long long cap = pow2ceil((unsigned long long)scale * need);
+            if (cap < 4096ull) cap = 4096ull;
+            caps[k] = cap;
+            base += cap;
+        }
+        unsigned long long spare = base < b->slot_cap ? b->slot_cap - base : 0ull;
+        for (int k = 0; k < count; ++k) {
+            const sssp_instance& x = h_inst[order[k]];
+            const long long units = (long long)x.n + x.m / 16;
+            if (units / 16384 < 16) continue;
+            unsigned long long extra = spare / caps[k];
+            if (extra > MAX_SEG - 1) extra = MAX_SEG - 1;
+            nsegs[k] = 1u + (unsigned)extra;
+            spare -= extra * caps[k];
+        }
+    }
     for (int k = 0; k < count; ++k) {
         const int i = order[k];
         const sssp_instance& x = h_inst[i];
-        unsigned long long need =
-            (unsigned long long)x.n + ((unsigned long long)x.m >> clog) + 1ull;
-        unsigned long long cap = pow2ceil((unsigned long long)scale * need);
-        if (cap < 4096ull) cap = 4096ull;
+        const unsigned long long cap = caps[k];
+        const unsigned nseg = nsegs[k];
         const size_t chunks = (size_t)((unsigned long long)x.m >> clog) + 1;
         const long long big = x.n > x.m ? x.n : x.m;
         const int ku = (int)((big + UNIT - 1) / UNIT);
-        if (slot_off + cap > b->slot_cap || chunk_off + chunks > b->chunk_cap ||
+        if (slot_off + nseg * cap > b->slot_cap || chunk_off + chunks > b->chunk_cap ||
             (size_t)(n_units + ku) > b->max_units)
             return BQ_EBUSY;
         InstDesc& d = b->h_desc[k];
         memset(&d, 0, sizeof d);
         SolveArgs& a = d.a;
         a.q.slots = b->slots + slot_off;
-        a.q.ctrl = b->ctrls + k;
+        a.q.ctrl = b->ctrls + (size_t)k * MAX_SEG;
         a.q.sig = a.q.ctrl;
         a.q.logN = bqh::log2_exact(cap);
         a.q.pad = 0;
@@ -475,7 +507,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         a.trace_shift = 0;
         a.trace_cap = 0;
         a.bwd = (L.flags & BQ_F_BWD) ? 1u : 0u;
-        a.nseg = 1;  // one queue per query
+        a.nseg = nseg;
         a.neginf = (L.flags & BQ_F_NEGINF) ? 1u : 0u;
         d.pred = (int*)x.pred;
         d.orig = i;
@@ -498,7 +530,8 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
             b->h_claim[n_claim++] = k;
         layout.push_back(cap);
         layout.push_back(slot_off);
-        slot_off += cap;
+        layout.push_back(nseg);
+        slot_off += nseg * cap;
         chunk_off += chunks;
     }
     hipStream_t cs = bqh::as_stream(stream);
@@ -507,7 +540,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
     // clean end; otherwise zero the slots and control blocks first
     if (b->dirty || layout != b->layout) {
         BQ_HIP_TRY(hipMemsetAsync(b->slots, 0, sizeof(unsigned long long) * slot_off, s));
-        BQ_HIP_TRY(hipMemsetAsync(b->ctrls, 0, sizeof(bq::Ctrl) * count, s));
+        BQ_HIP_TRY(hipMemsetAsync(b->ctrls, 0, sizeof(bq::Ctrl) * count * MAX_SEG, s));
         b->layout = layout;
         b->dirty = false;
     }
@@ -618,21 +651,42 @@ bq_status sssp_batch_autotune(sssp_batch* b, int32_t count, const sssp_instance*
                               const bq_launch* base, int32_t reps, bq_launch* h_best,
                               double* h_best_ms, void* stream) {
     if (!b || !h_inst || !h_best || !h_best_ms || count < 1) return BQ_EINVAL;
-    if (reps < 1) reps = 2;
+    if (reps < 1) reps = 3;
     bq_launch L = {};
     if (base) L = *base;
+    // shape bucket: powers of two of the query count and of the total
+    // vertices and edges, plus the caller's flags
+    unsigned long long tn = 0, tm = 0;
+    for (int i = 0; i < count; ++i) {
+        tn += (unsigned long long)(h_inst[i].n > 0 ? h_inst[i].n : 0);
+        tm += (unsigned long long)(h_inst[i].m > 0 ? h_inst[i].m : 0);
+    }
+    const unsigned long long bucket = ((unsigned long long)bqh::log2_exact(count) << 48) |
+                                      ((unsigned long long)bqh::log2_exact(tn + 1) << 40) |
+                                      ((unsigned long long)bqh::log2_exact(tm + 1) << 32) |
+                                      (unsigned long long)L.flags;
+    auto hit = b->tuned.find(bucket);
+    if (hit != b->tuned.end()) {
+        *h_best = hit->second.first;
+        *h_best_ms = hit->second.second;
+        return BQ_OK;
+    }
     std::vector<int32_t> neg(count);
     double best = 1e300;
     bq_launch bestL = L;
+    // median of the runs, and a 3 % margin before a new shape replaces the
+    // fastest so far (the work of asynchronous solves varies run to run)
     auto trial = [&](bq_launch t) -> bq_status {
-        double tmin = 1e300;
+        std::vector<double> ts;
         for (int r = 0; r < reps; ++r) {
             bq_status st = sssp_bf_batched(b, count, h_inst, neg.data(), &t, stream);
             if (st != BQ_OK) return st;
-            if (b->last.ms < tmin) tmin = b->last.ms;
+            ts.push_back(b->last.ms);
         }
-        if (tmin < best) {
-            best = tmin;
+        std::sort(ts.begin(), ts.end());
+        const double med = (ts[(ts.size() - 1) / 2] + ts[ts.size() / 2]) / 2.0;
+        if (med < best * (best < 1e300 ? 0.97 : 1.0)) {
+            best = med;
             bestL = t;
         }
         return BQ_OK;
@@ -660,15 +714,19 @@ bq_status sssp_batch_autotune(sssp_batch* b, int32_t count, const sssp_instance*
         if (st != BQ_OK) return st;
     }
     {
+        const bq_launch at = bestL;
+        for (int bb : {2, 4}) {
+            bq_launch t = at;
+            t.ticket_batch = bb;
+            bq_status st = trial(t);
+            if (st != BQ_OK) return st;
+        }
         bq_launch t = bestL;
-        t.ticket_batch = 2;
+        t.queue_scale = 1;  // queue capacity pow2(n + m/C + 1) instead of twice that
         bq_status st = trial(t);
         if (st != BQ_OK) return st;
-        t = bestL;
-        t.queue_scale = 1;  // queue capacity pow2(n + m/C + 1) instead of twice that
-        st = trial(t);
-        if (st != BQ_OK) return st;
     }
+    b->tuned[bucket] = std::make_pair(bestL, best);
     *h_best = bestL;
     *h_best_ms = best;
     return BQ_OK;

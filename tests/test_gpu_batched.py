@@ -127,6 +127,27 @@ def test_negative_cycle_marking_in_the_mix(batch):
     check_all(qs[:3] + qs[4:], keep[:3] + keep[4:], neg[:3] + neg[4:])
 
 
+def test_large_queries_get_segments(batch):
+    """Queries large enough to feed 16+ workgroups get up to 8 queue segments
+    when the slot arena has room; results stay exact, alone and mixed with
+    small queries, with and without a planted negative cycle (marking mode)."""
+    big = synth.rmat(18, 16, seed=41)
+    road = synth.road(600, plant_cycle=False, seed=42)
+    items = [(big, big.src, upload(big))]
+    qs, keep = make_queries(items)
+    check_all(qs, keep, batch.solve(qs))
+    items += [(road, 0, upload(road))] + mixed_graphs(43, 6)
+    qs, keep = make_queries(items)
+    check_all(qs, keep, batch.solve(qs, launch={"ticket_batch": 2}), method="fifo")
+    roadneg = synth.road(300, plant_cycle=True, seed=44)
+    qs, keep = make_queries([(roadneg, 0, upload(roadneg)), (big, big.src, upload(big))])
+    neg = batch.solve(qs, launch={"flags": pkg.BQ_F_NEGINF})
+    assert neg == [True, False]
+    torch.cuda.synchronize()
+    assert bool((qs[0][4] == np.iinfo(np.int64).min).all())
+    check_all(qs[1:], keep[1:], neg[1:], method="fifo")
+
+
 def test_shared_graph_many_sources(batch):
     g = synth.rmat(14, 16, seed=4)
     t = upload(g)

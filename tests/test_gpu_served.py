@@ -150,3 +150,29 @@ def test_engine_outputs_without_caller_buffers(graphs):
         deg = np.diff(g.offsets)
         assert x["reached_edges"] == int(deg[d_ref != oracle.INF].sum())
     srv.close()
+
+
+def test_large_requests_go_alone(graphs):
+    """Requests with work for 64+ workgroups are launched one per launch (so
+    they run with all queue segments); small ones are still batched, passing
+    over the large ones; every answer is exact."""
+    resident, uploads = graphs
+    big = synth.rmat(19, 16, seed=12)  # (n + m/16) / 16384 = 64
+    srv = make_server(resident + [big], lanes=2, max_batch=16)
+    rng = np.random.default_rng(13)
+    reqs, truth = [], []
+    for i in range(14):
+        gid = 3 if i % 3 == 0 else int(rng.integers(0, 3))
+        g = (resident + [big])[gid]
+        src = int(rng.integers(0, g.n))
+        reqs.append({"arrival_us": 0.0, "src": src, "graph": gid,
+                     "dist": torch.empty(g.n, dtype=torch.int64, device=DEV),
+                     "pred": torch.empty(g.n, dtype=torch.int32, device=DEV)})
+        truth.append((g, src))
+    resp, st = srv.run(reqs)
+    print(f"[served] size classes {st}", flush=True)
+    check(reqs, truth, resp)
+    n_big = sum(1 for r in reqs if r["graph"] == 3)
+    # every large request had a launch of its own; the 9 small ones shared
+    assert n_big + 1 <= st["launches"] < len(reqs)
+    srv.close()
