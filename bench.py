@@ -525,7 +525,7 @@ def main():
         queue_launch = json.loads(args.queue_launch)
     elif not args.sssp_only:
         best = None
-        for b in (1, 4, 16, 64):
+        for b in (1, 4, 16, 64, 256):
             for wgsz in (256, 1024):
                 for wgs in (64, 256, 0):
                     L = {"ticket_batch": b, "wg_size": wgsz, "wg_count": wgs}
@@ -544,7 +544,7 @@ def main():
     if not args.sssp_only:
         # the partitioned form (one Broker Queue per XCD, Alg. 2's layout)
         queue_part = {}
-        for b in (1, 64):
+        for b in (1, 64, 256):
             best = None
             for S in (4, 8):
                 L = {"ticket_batch": b, "wg_size": 1024, "wg_count": 0, "segments": S}

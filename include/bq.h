@@ -69,7 +69,7 @@ typedef struct {
                              (BQ_ETIMEOUT), so no launch runs unbounded. */
     int32_t row_chunk;    /* solver: rows longer than this many edges are split
                              into queue items of this size (power of two,
-                             64..65536); 0 = 1024 */
+                             64..65536); 0 = 256 */
     int32_t queue_scale;  /* batched solver: each query's queue holds
                              pow2(queue_scale * (n + m/row_chunk + 1)) slots,
                              1 or 2; 0 = 2 */
@@ -264,13 +264,12 @@ bq_status sssp_bf(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
  * workgroup counts 4, 8, 16, ... up to the co-resident maximum (stopping
  * once clearly past the fastest) and 3/4 and 3/2 of the fastest, then
  * ticket batches b = 2, 4 around the
- * fastest count, then row chunks 256 and 4096 at the fastest shape, then
+ * fastest count, then row chunks 1024 and 4096 at the fastest shape, then
  * 1, 2 and 4 queue segments against the default; `reps` runs per candidate
  * (0 = 5), compared by their median, a candidate replacing the fastest so
- * far only when at least 3 % faster; a winner with another ticket batch, row
- * chunk or segment count is finally run against the plain shape (best
- * count, b = 1), 2 * reps times each, alternating, and kept only if its
- * median is lower.
+ * far only when at least 3 % faster; a winner that differs from the best
+ * power-of-two count with default settings is finally run against it,
+ * 2 * reps times each, alternating, and kept only if its median is lower.
  * *h_best gets the fastest launch (other fields copied from `base`, which
  * may be NULL), *h_best_ms its time. Synchronous. */
 bq_status sssp_autotune(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
@@ -281,10 +280,11 @@ bq_status sssp_autotune(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_of
 /* Work counters and device time of the last call on ctx. */
 bq_status sssp_last_stats(const sssp_ctx* ctx, sssp_stats* h_out);
 
-/* Timeline of the last sssp_bf call made with BQ_F_TRACE: up to cap_samples
- * samples of 4 uint64 each, (time since start in 10 ns ticks, items dequeued
- * so far, queue length, pending work); one sample each time the dequeued
- * work crosses a multiple of 2^k items (k chosen from n and m), unused
+/* Timeline of the last sssp_bf call made with BQ_F_TRACE (one vertex queue):
+ * up to cap_samples samples of 4 uint64 each, (time since start in 10 ns
+ * ticks, vertex items dequeued so far, vertex queue length, pending work
+ * including the waves' unpaid debts); one sample each time the dequeued
+ * vertex items cross a multiple of 2^k (k chosen from n and m), unused
  * samples all ones. Returns the number of samples written, or BQ_EINVAL. */
 int32_t sssp_last_trace(const sssp_ctx* ctx, uint64_t* h_out, int32_t cap_samples);
 

@@ -5,6 +5,7 @@
 #include <limits.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <algorithm>
 #include <vector>
@@ -39,15 +40,15 @@ struct sssp_ctx {
 
 namespace {
 
-constexpr unsigned DEFAULT_CHUNK_LOG = 10;  // rows longer than 1024 edges are split
+constexpr unsigned DEFAULT_CHUNK_LOG = 8;   // rows longer than 256 edges are split
 constexpr unsigned MIN_CHUNK_LOG = 6;       // smallest row chunk a launch may ask for
 constexpr unsigned MAX_CHUNK_LOG = 16;
 constexpr int TRACE_CAP = 4096;
 
 bq_status ctx_reset_queue(sssp_ctx* c, hipStream_t s) {
     BQ_HIP_TRY(hipMemsetAsync(c->slots, 0,
-                              sizeof(unsigned long long) * c->capacity * MAX_SEG, s));
-    BQ_HIP_TRY(hipMemsetAsync(c->ctrl, 0, sizeof(bq::Ctrl) * MAX_SEG, s));
+                              sizeof(unsigned long long) * c->capacity * MAX_Q, s));
+    BQ_HIP_TRY(hipMemsetAsync(c->ctrl, 0, sizeof(bq::Ctrl) * MAX_Q, s));
     c->dirty = false;
     return BQ_OK;
 }
@@ -145,11 +146,11 @@ bq_status sssp_ctx_create(int32_t max_n, int64_t max_m, sssp_ctx** out) {
     c->capacity = (uint32_t)cap;
     c->logN = bqh::log2_exact(cap);
     const size_t chunks = (size_t)((unsigned long long)max_m >> MIN_CHUNK_LOG) + 1;
-    if (hipMalloc(&c->slots, sizeof(unsigned long long) * cap * MAX_SEG) != hipSuccess ||
+    if (hipMalloc(&c->slots, sizeof(unsigned long long) * cap * MAX_Q) != hipSuccess ||
         hipMalloc(&c->trace, sizeof(unsigned long long) * 4 * TRACE_CAP) != hipSuccess ||
         hipHostMalloc(&c->h_trace, sizeof(unsigned long long) * 4 * TRACE_CAP,
                       hipHostMallocDefault) != hipSuccess ||
-        hipMalloc(&c->ctrl, sizeof(bq::Ctrl) * MAX_SEG) != hipSuccess ||
+        hipMalloc(&c->ctrl, sizeof(bq::Ctrl) * MAX_Q) != hipSuccess ||
         hipMalloc(&c->chunk_owner, sizeof(unsigned) * chunks) != hipSuccess ||
         hipMalloc(&c->wrange, sizeof(int) * 2 * INIT_MAX_BLOCKS) != hipSuccess ||
         hipHostMalloc(&c->h_ctrl, sizeof(bq::Ctrl), hipHostMallocDefault) != hipSuccess) {
@@ -244,6 +245,7 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
             if (st != BQ_OK) return st;
         }
     }
+    const bq_launch pow2L = bestL;  // the best power-of-two count, defaults otherwise
     // counts between the powers of two around the best
     for (int wgs : {best_wgs * 3 / 4, best_wgs * 3 / 2}) {
         if (wgs < 1 || wgs > max_grid || wgs == best_wgs) continue;
@@ -265,7 +267,7 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
     // row chunk around the default at the best shape so far
     {
         const bq_launch cur = bestL;
-        for (int chunk : {256, 4096}) {
+        for (int chunk : {1024, 4096}) {
             double ms = 0;
             bq_status st = trial(cur.wg_count, cur.ticket_batch, &ms, chunk);
             if (st != BQ_OK) return st;
@@ -282,19 +284,15 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
             if (st != BQ_OK) return st;
         }
     }
-    // confirmation: the winner against the plain shape (the best count at
-    // b = 1 with the caller's other fields), alternating runs, so that one
-    // lucky series cannot pick a shape that is slower on average
-    if (bestL.ticket_batch != 1 || bestL.row_chunk != L.row_chunk ||
-        bestL.segments != L.segments) {
-        bq_launch plain = L;
-        plain.wg_count = best_wgs;
-        plain.ticket_batch = 1;
+    // confirmation: the winner against the best power-of-two count with
+    // default settings, alternating runs, so that one lucky series cannot
+    // pick a shape that is slower on average
+    if (memcmp(&bestL, &pow2L, sizeof bestL) != 0) {
         std::vector<double> ta, tb;
         for (int r = 0; r < 2 * reps; ++r) {
             for (int side = 0; side < 2; ++side) {
                 int32_t neg = 0;
-                bq_launch t = side ? plain : bestL;
+                bq_launch t = side ? pow2L : bestL;
                 bq_status st = sssp_bf(c, n, m, d_offsets, d_cols, d_w, src, d_dist, nullptr,
                                        &neg, &t, stream);
                 if (st != BQ_OK) return st;
@@ -305,7 +303,7 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
         std::sort(tb.begin(), tb.end());
         const double ma = ta[ta.size() / 2], mb = tb[tb.size() / 2];
         if (mb <= ma) {
-            bestL = plain;
+            bestL = pow2L;
             best = mb;
         } else {
             best = ma;

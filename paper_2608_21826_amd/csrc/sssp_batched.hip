@@ -101,7 +101,7 @@ __global__ __launch_bounds__(BINIT_WG) void k_binit(const InstDesc* D, const Uni
                 c->error.v = 0ull;
                 c->negcycle.v = 0ull;
                 c->aux[0].v = (unsigned long long)(d.unit_end - d.unit_begin);
-                for (unsigned sg = 0; sg < a.nseg; ++sg)  // dequeue positions at start
+                for (unsigned sg = 0; sg < 2 * a.nseg; ++sg)  // dequeue positions at start
                     c[sg].aux[2].v = c[sg].head.v;
                 c->aux[4].v = bq::now_ticks();
                 c->aux[5].v = 0ull;  // finished flag
@@ -308,14 +308,14 @@ bq_status sssp_batch_create(int32_t max_instances, int64_t max_total_n, int64_t 
     b->max_m = max_total_m;
     // per query: capacity pow2(scale * (n + m/C + 1)) with scale <= 2 and
     // C >= 64, at least 4096 -> at most 4 * (n + m/64 + 1) + 4096 each
-    b->slot_cap = (size_t)(4 * (max_total_n + max_total_m / 64 + max_instances)) +
-                  (size_t)max_instances * 4096;
+    b->slot_cap = 2 * ((size_t)(4 * (max_total_n + max_total_m / 64 + max_instances)) +
+                       (size_t)max_instances * 4096);  // vertex queue + chunk lane
     b->chunk_cap = (size_t)(max_total_m / 64 + max_instances);
     b->max_units = (size_t)((max_total_n + max_total_m) / UNIT + 2 * max_instances);
     b->max_claim = (size_t)(8 * 4096 + max_instances);
     if (hipMalloc(&b->slots, sizeof(unsigned long long) * b->slot_cap) != hipSuccess ||
         hipMalloc(&b->chunks, sizeof(unsigned) * b->chunk_cap) != hipSuccess ||
-        hipMalloc(&b->ctrls, sizeof(bq::Ctrl) * max_instances * MAX_SEG) != hipSuccess ||
+        hipMalloc(&b->ctrls, sizeof(bq::Ctrl) * max_instances * MAX_Q) != hipSuccess ||
         hipMalloc(&b->d_desc, sizeof(InstDesc) * max_instances) != hipSuccess ||
         hipMalloc(&b->d_units, sizeof(Unit) * b->max_units) != hipSuccess ||
         hipMalloc(&b->d_claim, sizeof(int) * b->max_claim) != hipSuccess ||
@@ -344,7 +344,7 @@ bq_status sssp_batch_create(int32_t max_instances, int64_t max_total_n, int64_t 
     BQ_HIP_TRY(hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
     b->dirty = true;
     BQ_HIP_TRY(hipMemsetAsync(b->slots, 0, sizeof(unsigned long long) * b->slot_cap, b->stream));
-    BQ_HIP_TRY(hipMemsetAsync(b->ctrls, 0, sizeof(bq::Ctrl) * max_instances * MAX_SEG,
+    BQ_HIP_TRY(hipMemsetAsync(b->ctrls, 0, sizeof(bq::Ctrl) * max_instances * MAX_Q,
                               b->stream));
     BQ_HIP_TRY(hipStreamSynchronize(b->stream));
     b->dirty = false;
@@ -457,17 +457,17 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
             unsigned long long cap = pow2ceil((unsigned long long)scale * need);
             if (cap < 4096ull) cap = 4096ull;
             caps[k] = cap;
-            base += cap;
+            base += 2 * cap;
         }
         unsigned long long spare = base < b->slot_cap ? b->slot_cap - base : 0ull;
         for (int k = 0; k < count; ++k) {
             const sssp_instance& x = h_inst[order[k]];
             const long long units = (long long)x.n + x.m / 16;
             if (units / 16384 < 16) continue;
-            unsigned long long extra = spare / caps[k];
+            unsigned long long extra = spare / (2 * caps[k]);
             if (extra > MAX_SEG - 1) extra = MAX_SEG - 1;
             nsegs[k] = 1u + (unsigned)extra;
-            spare -= extra * caps[k];
+            spare -= 2 * extra * caps[k];
         }
     }
     for (int k = 0; k < count; ++k) {
@@ -478,14 +478,14 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         const size_t chunks = (size_t)((unsigned long long)x.m >> clog) + 1;
         const long long big = x.n > x.m ? x.n : x.m;
         const int ku = (int)((big + UNIT - 1) / UNIT);
-        if (slot_off + nseg * cap > b->slot_cap || chunk_off + chunks > b->chunk_cap ||
+        if (slot_off + 2 * nseg * cap > b->slot_cap || chunk_off + chunks > b->chunk_cap ||
             (size_t)(n_units + ku) > b->max_units)
             return BQ_EBUSY;
         InstDesc& d = b->h_desc[k];
         memset(&d, 0, sizeof d);
         SolveArgs& a = d.a;
         a.q.slots = b->slots + slot_off;
-        a.q.ctrl = b->ctrls + (size_t)k * MAX_SEG;
+        a.q.ctrl = b->ctrls + (size_t)k * MAX_Q;
         a.q.sig = a.q.ctrl;
         a.q.logN = bqh::log2_exact(cap);
         a.q.pad = 0;
@@ -531,7 +531,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         layout.push_back(cap);
         layout.push_back(slot_off);
         layout.push_back(nseg);
-        slot_off += nseg * cap;
+        slot_off += 2 * nseg * cap;  // vertex queues and their chunk lanes
         chunk_off += chunks;
     }
     hipStream_t cs = bqh::as_stream(stream);
@@ -540,7 +540,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
     // clean end; otherwise zero the slots and control blocks first
     if (b->dirty || layout != b->layout) {
         BQ_HIP_TRY(hipMemsetAsync(b->slots, 0, sizeof(unsigned long long) * slot_off, s));
-        BQ_HIP_TRY(hipMemsetAsync(b->ctrls, 0, sizeof(bq::Ctrl) * count * MAX_SEG, s));
+        BQ_HIP_TRY(hipMemsetAsync(b->ctrls, 0, sizeof(bq::Ctrl) * count * MAX_Q, s));
         b->layout = layout;
         b->dirty = false;
     }

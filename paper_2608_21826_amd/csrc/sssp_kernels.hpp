@@ -55,7 +55,7 @@ __global__ __launch_bounds__(INIT_WG) void k_init(Queue q, long long* key, int n
     c->error.v = 0ull;
     c->negcycle.v = 0ull;
     c->aux[0].v = (unsigned long long)gridDim.x;  // number of weight-range partials
-    for (unsigned sg = 0; sg < MAX_SEG; ++sg)      // dequeue positions at start
+    for (unsigned sg = 0; sg < MAX_Q; ++sg)        // dequeue positions at start
         q.ctrl[sg].aux[2].v = q.ctrl[sg].head.v;
     c->aux[4].v = bq::now_ticks();                // clock at start
     for (int i = 0; i < bq::ST_N; ++i) c->stats[i].v = 0ull;
