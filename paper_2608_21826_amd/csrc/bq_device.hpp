@@ -88,16 +88,17 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
     return x;
 }
 
-template <class T>
-__device__ __forceinline__ T ld_rlx(const T* p) {
+// relaxed agent-scope atomics; P is a pointer in any address space
+template <class P>
+__device__ __forceinline__ auto ld_rlx(P p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-template <class T>
-__device__ __forceinline__ void st_rlx(T* p, T v) {
+template <class P, class V>
+__device__ __forceinline__ void st_rlx(P p, V v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-template <class T>
-__device__ __forceinline__ T add_rlx(T* p, T v) {
+template <class P, class V>
+__device__ __forceinline__ auto add_rlx(P p, V v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
@@ -144,11 +145,24 @@ __device__ __forceinline__ unsigned long long now_ticks() { return wall_clock64(
 // stores (2r+2, 0). Coherence of that one word orders everything, so no
 // cross-XCD fence (L2 writeback / invalidate) is needed per operation.
 // ---------------------------------------------------------------------------
+// Device memory pointers kept in structures. In device code they are typed
+// as global-memory pointers, so that accesses through a structure loaded
+// from memory (the batched form's per-query descriptors) compile to global
+// loads, stores and atomics rather than flat ones, which would also count
+// against the LDS wait counter. Host code sees plain pointers and assigns
+// them with a cast to the field's type.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define BQ_GLOBAL __attribute__((address_space(1)))
+#else
+#define BQ_GLOBAL
+#endif
+
 struct Queue {
-    unsigned long long* slots;  // [N] (ticket << 32 | payload)
-    Ctrl* ctrl;                 // head, tail, count of this queue
-    Ctrl* sig;                  // abort / error words (the same block, or the
-                                // first segment's for a segment of a split queue)
+    BQ_GLOBAL unsigned long long* slots;  // [N] (ticket << 32 | payload)
+    BQ_GLOBAL Ctrl* ctrl;                 // head, tail, count of this queue
+    BQ_GLOBAL Ctrl* sig;                  // abort / error words (the same block, or
+                                          // the first segment's for a segment of a
+                                          // split queue)
     uint32_t logN;
     uint32_t pad;
     unsigned long long N;
@@ -185,7 +199,7 @@ struct Watch {
 // batch. Reserve k on count; the first min(k, N - old) are ensured, the rest
 // are given back. Returns the number ensured.
 __device__ __forceinline__ uint32_t reserve_enqueue(const Queue& q, uint32_t k) {
-    long long* cnt = reinterpret_cast<long long*>(&q.ctrl->count.v);
+    BQ_GLOBAL long long* cnt = (BQ_GLOBAL long long*)(&q.ctrl->count.v);
     long long num = ld_rlx(cnt);
     if (num >= (long long)q.N) return 0;
     long long old = add_rlx(cnt, (long long)k);
@@ -203,7 +217,7 @@ __device__ __forceinline__ uint32_t reserve_enqueue(const Queue& q, uint32_t k) 
 // count is skipped and k is asked for directly.
 __device__ __forceinline__ uint32_t reserve_dequeue(const Queue& q, uint32_t k,
                                                     bool optimistic = false) {
-    long long* cnt = reinterpret_cast<long long*>(&q.ctrl->count.v);
+    BQ_GLOBAL long long* cnt = (BQ_GLOBAL long long*)(&q.ctrl->count.v);
     if (!optimistic) {
         long long num = ld_rlx(cnt);
         if (num <= 0) return 0;
@@ -228,7 +242,7 @@ __device__ __forceinline__ uint32_t ensure_dequeue(const Queue& q, uint32_t k, b
     if (bwd) return reserve_dequeue(q, k, true);
     uint32_t e = reserve_dequeue(q, k, optimistic);
     for (int again = 0; e == 0 && again < 3; ++again) {
-        if (ld_rlx(reinterpret_cast<long long*>(&q.ctrl->count.v)) <= 0) break;
+        if (ld_rlx((BQ_GLOBAL long long*)(&q.ctrl->count.v)) <= 0) break;
         e = reserve_dequeue(q, k, false);
     }
     return e;

@@ -38,9 +38,9 @@ namespace {
 __device__ __forceinline__ Queue view(unsigned long long* sl, bq::Ctrl* c, uint32_t logN,
                                       bq::Ctrl* sig) {
     Queue q;
-    q.slots = sl;
-    q.ctrl = c;
-    q.sig = sig;
+    q.slots = (decltype(q.slots))sl;
+    q.ctrl = (decltype(q.ctrl))c;
+    q.sig = (decltype(q.sig))sig;
     q.logN = logN;
     q.pad = 0;
     q.N = 1ull << logN;

@@ -55,9 +55,9 @@ bq_status ctx_reset_queue(sssp_ctx* c, hipStream_t s) {
 
 Queue ctx_queue(const sssp_ctx* c) {
     Queue q;
-    q.slots = c->slots;
-    q.ctrl = c->ctrl;
-    q.sig = c->ctrl;
+    q.slots = (decltype(q.slots))c->slots;
+    q.ctrl = (decltype(q.ctrl))c->ctrl;
+    q.sig = (decltype(q.sig))c->ctrl;
     q.logN = c->logN;
     q.pad = 0;
     q.N = 1ull << c->logN;
@@ -377,12 +377,12 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     const unsigned shift = key_shift(n);
     SolveArgs a;
     a.q = q;
-    a.off = (const long long*)d_offsets;
-    a.col = (const int*)d_cols;
-    a.w = (const int*)d_w;
-    a.key = (long long*)d_dist;
-    a.chunk_owner = c->chunk_owner;
-    a.wrange = c->wrange;
+    a.off = (decltype(a.off))d_offsets;
+    a.col = (decltype(a.col))d_cols;
+    a.w = (decltype(a.w))d_w;
+    a.key = (decltype(a.key))d_dist;
+    a.chunk_owner = (decltype(a.chunk_owner))c->chunk_owner;
+    a.wrange = (decltype(a.wrange))c->wrange;
     a.n = n;
     a.src = src;
     a.m = (long long)m;
@@ -401,7 +401,7 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
         unsigned long long unit = (unsigned long long)n + ((unsigned long long)m >> clog);
         unsigned sh = 0;
         while ((1ull << (sh + 8)) < unit) ++sh;
-        a.trace = c->trace;
+        a.trace = (decltype(a.trace))c->trace;
         a.trace_shift = sh;
         BQ_HIP_TRY(hipMemsetAsync(c->trace, 0xff, sizeof(unsigned long long) * 4 * TRACE_CAP, s));
     }

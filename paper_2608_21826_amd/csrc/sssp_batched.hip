@@ -119,7 +119,10 @@ __global__ __launch_bounds__(BINIT_WG) void k_binit(const InstDesc* D, const Uni
 }
 
 template <int B>
-__global__ __launch_bounds__(SOLVE_WG, SSSP_MIN_WAVES) void k_bsolve(const InstDesc* D, int count,
+// D is read-only for the whole launch (__restrict__): its uniform loads then
+// go through the scalar cache, and the descriptor of the query a workgroup
+// works on stays in scalar registers instead of taking vector ones.
+__global__ __launch_bounds__(SOLVE_WG, SSSP_MIN_WAVES) void k_bsolve(const InstDesc* __restrict__ D, int count,
                                                      const int* claim, int n_claim,
                                                      BatchCtl* bc) {
     __shared__ WaveLds<B> lds[WAVES_PER_WG];
@@ -151,7 +154,7 @@ __global__ __launch_bounds__(SOLVE_WG, SSSP_MIN_WAVES) void k_bsolve(const InstD
             S.done = 0;
         }
         __syncthreads();
-        const int i = s_inst;
+        const int i = __builtin_amdgcn_readfirstlane(s_inst);  // workgroup-uniform
         if (i < 0) break;
         const SolveArgs a = D[i].a;
         solve_instance<B>(a, L, S, wid, st);
@@ -484,18 +487,18 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         InstDesc& d = b->h_desc[k];
         memset(&d, 0, sizeof d);
         SolveArgs& a = d.a;
-        a.q.slots = b->slots + slot_off;
-        a.q.ctrl = b->ctrls + (size_t)k * MAX_Q;
-        a.q.sig = a.q.ctrl;
+        a.q.slots = (decltype(a.q.slots))(b->slots + slot_off);
+        a.q.ctrl = (decltype(a.q.ctrl))(b->ctrls + (size_t)k * MAX_Q);
+        a.q.sig = (decltype(a.q.sig))a.q.ctrl;
         a.q.logN = bqh::log2_exact(cap);
         a.q.pad = 0;
         a.q.N = cap;
-        a.off = (const long long*)x.offsets;
-        a.col = (const int*)x.cols;
-        a.w = (const int*)x.w;
-        a.key = (long long*)x.dist;
-        a.chunk_owner = b->chunks + chunk_off;
-        a.wrange = b->d_partials + 2 * n_units;
+        a.off = (decltype(a.off))x.offsets;
+        a.col = (decltype(a.col))x.cols;
+        a.w = (decltype(a.w))x.w;
+        a.key = (decltype(a.key))x.dist;
+        a.chunk_owner = (decltype(a.chunk_owner))(b->chunks + chunk_off);
+        a.wrange = (decltype(a.wrange))(b->d_partials + 2 * n_units);
         a.n = x.n;
         a.src = x.src;
         a.m = (long long)x.m;

@@ -109,12 +109,12 @@ constexpr int U = SSSP_UNROLL;  // edges per lane per pipelined step
 
 struct SolveArgs {
     Queue q;
-    const long long* off;
-    const int* col;
-    const int* w;
-    long long* key;          // the caller's dist buffer, used as key array
-    unsigned* chunk_owner;   // [m >> chunk_log + 1]
-    const int* wrange;       // per-block (min w, max w) from k_init
+    BQ_GLOBAL const long long* off;
+    BQ_GLOBAL const int* col;
+    BQ_GLOBAL const int* w;
+    BQ_GLOBAL long long* key;  // the caller's dist buffer, used as key array
+    BQ_GLOBAL unsigned* chunk_owner;  // [m >> chunk_log + 1]
+    BQ_GLOBAL const int* wrange;  // per-block (min w, max w) from k_init
     int n;
     int src;
     long long m;
@@ -122,7 +122,7 @@ struct SolveArgs {
     unsigned chunk_log;
     unsigned long long limit;     // one wait (ticks of the 100 MHz clock)
     unsigned long long deadline;  // whole solve
-    unsigned long long* trace;    // optional timeline: 4 words per sample
+    BQ_GLOBAL unsigned long long* trace;  // optional timeline: 4 words per sample
     unsigned trace_shift;         // one sample per 2^trace_shift dequeued items
     unsigned trace_cap;           // samples
     unsigned bwd;                 // dequeue broker policy: 0 Broker Queue, 1 BWD
@@ -183,7 +183,7 @@ __device__ bool flush_out(const SolveArgs& a, const Queue& seg, const unsigned* 
         // are bounded, and each segment holds twice that, so count + cnt <= N
         // always; an overflow would be a bug and stops the solve.
         if (need > 0) bq::add_rlx(&q.ctrl->pending.v, (unsigned long long)need);
-        const long long old = bq::add_rlx(reinterpret_cast<long long*>(&seg.ctrl->count.v),
+        const long long old = bq::add_rlx((BQ_GLOBAL long long*)(&seg.ctrl->count.v),
                                           (long long)cnt);
         base = bq::add_rlx(&seg.ctrl->tail.v, (unsigned long long)cnt);
         if (old + cnt > (long long)seg.N) bq::raise_error(q, bq::ERR_FULL);
@@ -354,7 +354,7 @@ __device__ int idle_wait(const SolveArgs& a, WgShared& S, int wid, unsigned long
                 long long cnt = 0;
                 if ((unsigned)lane < 2u * a.nseg) {
                     const bq::Ctrl* c = q.ctrl + lane;
-                    cnt = bq::ld_rlx(reinterpret_cast<const long long*>(&c->count.v));
+                    cnt = bq::ld_rlx((BQ_GLOBAL const long long*)(&c->count.v));
                     hd = bq::ld_rlx(&c->head.v);
                 }
                 if (lane == 0) pend = bq::ld_rlx(&q.ctrl->pending.v);
@@ -516,7 +516,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, in
             long long c = 0;
             if ((unsigned)lane < 2u * a.nseg && (unsigned)lane != home &&
                 (unsigned)lane != a.nseg + home)
-                c = bq::ld_rlx(reinterpret_cast<const long long*>(&(q.ctrl + lane)->count.v));
+                c = bq::ld_rlx((BQ_GLOBAL const long long*)(&(q.ctrl + lane)->count.v));
             // wave arg-max of (count, lane)
             long long best = c > 0 ? c : 0;
             int who = lane;

@@ -204,7 +204,7 @@ __global__ __launch_bounds__(ROUND_MAX_WG) void k_round(RoundArgs a) {
     while (true) {
         unsigned e = 0;
         unsigned long long base = 0;
-        if (lane == 0 && (!look || bq::ld_rlx(reinterpret_cast<const long long*>(&c->count.v)) > 0)) {
+        if (lane == 0 && (!look || bq::ld_rlx((BQ_GLOBAL const long long*)(&c->count.v)) > 0)) {
             e = bq::ensure_dequeue(q, (unsigned)K, optimistic, a.bwd != 0);
             if (e) base = bq::add_rlx(&c->head.v, (unsigned long long)e);
         }
@@ -506,9 +506,9 @@ bq_status sssp_bf_rounds(sssp_rounds_ctx* c, int32_t n, int64_t m, const int64_t
     if (grid > max_grid) grid = max_grid;  // waits need every wave resident
 
     RoundArgs a;
-    a.q.slots = c->slots;
-    a.q.ctrl = c->ctrl;
-    a.q.sig = c->ctrl;
+    a.q.slots = (decltype(a.q.slots))c->slots;
+    a.q.ctrl = (decltype(a.q.ctrl))c->ctrl;
+    a.q.sig = (decltype(a.q.sig))c->ctrl;
     a.q.logN = c->logN;
     a.q.pad = 0;
     a.q.N = 1ull << c->logN;
