@@ -69,7 +69,8 @@ typedef struct {
                              (BQ_ETIMEOUT), so no launch runs unbounded. */
     int32_t row_chunk;    /* solver: rows longer than this many edges are split
                              into queue items of this size (power of two,
-                             64..65536); 0 = 256 */
+                             64..65536); 0 = 128 for sssp_bf, 1024 for
+                             the batched form */
     int32_t queue_scale;  /* batched solver: each query's queue holds
                              pow2(queue_scale * (n + m/row_chunk + 1)) slots,
                              1 or 2; 0 = 2 */
@@ -264,7 +265,7 @@ bq_status sssp_bf(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
  * workgroup counts 4, 8, 16, ... up to the co-resident maximum (stopping
  * once clearly past the fastest) and 3/4 and 3/2 of the fastest, then
  * ticket batches b = 2, 4 around the
- * fastest count, then row chunks 1024 and 4096 at the fastest shape, then
+ * fastest count, then row chunks 64 and 256 at the fastest shape, then
  * 1, 2 and 4 queue segments against the default; `reps` runs per candidate
  * (0 = 5), compared by their median, a candidate replacing the fastest so
  * far only when at least 3 % faster; a winner that differs from the best

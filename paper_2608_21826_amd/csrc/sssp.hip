@@ -40,7 +40,7 @@ struct sssp_ctx {
 
 namespace {
 
-constexpr unsigned DEFAULT_CHUNK_LOG = 8;   // rows longer than 256 edges are split
+constexpr unsigned DEFAULT_CHUNK_LOG = 7;   // rows longer than 128 edges are split
 constexpr unsigned MIN_CHUNK_LOG = 6;       // smallest row chunk a launch may ask for
 constexpr unsigned MAX_CHUNK_LOG = 16;
 constexpr int TRACE_CAP = 4096;
@@ -267,7 +267,7 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
     // row chunk around the default at the best shape so far
     {
         const bq_launch cur = bestL;
-        for (int chunk : {1024, 4096}) {
+        for (int chunk : {64, 256}) {
             double ms = 0;
             bq_status st = trial(cur.wg_count, cur.ticket_batch, &ms, chunk);
             if (st != BQ_OK) return st;
