@@ -390,11 +390,11 @@ def rounds_leg(pkg, torch, g, off, col, w, ref_dist, m_reached, reps=5):
 
 def bf_sweep(pkg, torch, dev, steps=3):
     """Queue-driven Bellman-Ford under both broker policies (Broker Queue,
-    BWD), with one queue and with 8 segments, over the paper's block counts
-    64 / 108 / 216, then 512 and the co-resident maximum (8 per CU is more
-    than fits; the library clamps), for ticket batch b = 1 and 4, on RMAT-20
-    and the 2048^2 road graph. Every run's distances must equal the first
-    run's. Returns rows of GTEPS."""
+    BWD), with one queue and with 2 and 8 segments, over the paper's block
+    counts 64 / 108 / 216, then 512 and the co-resident maximum (8 per CU is
+    more than fits; the library clamps), for ticket batch b = 1 and 4, at the
+    default row chunk, on RMAT-20 and the 2048^2 road graph. Every run's
+    distances must equal the first run's. Returns rows of GTEPS."""
     rows = []
     for name in ("rmat20", "road2048"):
         g = synth.config_graph(name)
@@ -407,10 +407,10 @@ def bf_sweep(pkg, torch, dev, steps=3):
         ref = ref.clone()
         reached = (ref != np.iinfo(np.int64).max).cpu().numpy()
         m_reached = int(np.diff(g.offsets)[reached].sum())
-        for bwd, seg in ((False, 1), (True, 1), (False, 8), (True, 8)):
+        for bwd, seg in ((False, 1), (True, 1), (False, 2), (True, 2), (False, 8), (True, 8)):
             for b in (1, 4):
                 for wgs in (64, 108, 216, 512, 8 * pkg.device_cus()):
-                    L = {"ticket_batch": b, "wg_count": wgs, "row_chunk": 256,
+                    L = {"ticket_batch": b, "wg_count": wgs,
                          "flags": pkg.BQ_F_BWD if bwd else 0, "segments": seg}
                     best = None
                     for _ in range(steps):
