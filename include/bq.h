@@ -428,7 +428,9 @@ typedef struct {
     double service_us;        /* launch queued -> completion */
     int64_t reached_edges;    /* edges whose source vertex was reached */
     int32_t neg_cycle;
-    int32_t status;           /* bq_status of the request (BQ_EINVAL / BQ_EBUSY if rejected) */
+    int32_t status;           /* bq_status of the request: BQ_EINVAL / BQ_EBUSY if
+                                 rejected, BQ_EHIP if its upload failed, else the
+                                 status of its batched launch */
 } bq_response;
 
 typedef struct {
@@ -461,7 +463,9 @@ bq_status bq_server_add_graph(bq_server* s, int32_t n, int64_t m, const int64_t*
  * free lane's limits; every free lane starts one batched launch with what is
  * admitted, so requests arriving while others run are launched on other
  * lanes and overlap with them. Fills resp[i] per request and *stats
- * (may be NULL). Returns when every request is done. */
+ * (may be NULL). Returns when every request is done; a failing request
+ * (rejected, upload or launch error) ends with its own status and does not
+ * stop the others. */
 bq_status bq_server_run(bq_server* s, int32_t count, const bq_request* reqs,
                         bq_response* resp, bq_server_stats* stats);
 

@@ -355,7 +355,6 @@ bq_status bq_server_run(bq_server* s, int32_t count, const bq_request* reqs,
                 q.m = nd.m;
                 q.src = r.src;
                 if (up) {
-                    L.blocks.push_back(off_up);
                     char* base = s->d_arena + off_up;
                     int64_t* d_off = (int64_t*)base;
                     int32_t* d_col = (int32_t*)(base + (((uint64_t)(nd.n + 1) * 8 + 255) & ~255ull));
@@ -366,8 +365,18 @@ bq_status bq_server_run(bq_server* s, int32_t count, const bq_request* reqs,
                          (hipMemcpyAsync(d_col, r.h_cols, (size_t)nd.m * 4, hipMemcpyHostToDevice,
                                          L.stream) != hipSuccess ||
                           hipMemcpyAsync(d_w, r.h_w, (size_t)nd.m * 4, hipMemcpyHostToDevice,
-                                         L.stream) != hipSuccess)))
-                        return BQ_EHIP;
+                                         L.stream) != hipSuccess))) {
+                        // this request fails; the lanes and the rest of the
+                        // trace go on (its memory is not used by any launch)
+                        bq_arena_free(s->arena, off_up);
+                        if (!r.d_dist) bq_arena_free(s->arena, off_out);
+                        resp[i].status = BQ_EHIP;
+                        resp[i].latency_us = now_us() - r.arrival_us;
+                        ++done;
+                        progress = true;
+                        continue;
+                    }
+                    L.blocks.push_back(off_up);
                     upload_total += upload_bytes(nd.n, nd.m);
                     q.offsets = d_off;
                     q.cols = d_col;
