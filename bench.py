@@ -183,6 +183,10 @@ def run_probes(pkg, torch, dev):
         ms = min(pkg.probe(1, t, sink, size=words, ops_per_lane=opl, grid=grid, block=block)
                  for _ in range(3))
         res[f"atomic_min_rand_{name}_Gops"] = round(grid * block * opl / ms / 1e6, 2)
+        pkg.probe(5, t, sink, size=words, ops_per_lane=opl, grid=grid, block=block)
+        ms = min(pkg.probe(5, t, sink, size=words, ops_per_lane=opl, grid=grid, block=block)
+                 for _ in range(3))
+        res[f"load_rand_{name}_Gops"] = round(grid * block * opl / ms / 1e6, 2)
         del t
     word = torch.zeros(2, dtype=torch.int64, device=dev)
     grid, block, opl = 4 * cus, 256, 8
@@ -631,6 +635,11 @@ def main():
             # relaxations are mostly loads (the key check), not atomics
             out["relax_rate_vs_atomic_peak"] = round(
                 (rel / (k_ms.mean() * 1e-3) / 1e9) / peak, 4)
+        lpeak = probes.get("load_rand_8MiB_Gops")
+        if lpeak:
+            # one random coherent key load per relaxation at most
+            out["relax_rate_vs_load_peak"] = round(
+                (rel / (k_ms.mean() * 1e-3) / 1e9) / lpeak, 4)
     if not args.sssp_only:
         out["rounds_form"] = rounds_leg(pkg, torch, g, off, col, w, dist, m_reached)
         log(f"rounds form {out['rounds_form']}")

@@ -343,7 +343,14 @@ bq_status sssp_rounds_last_stats(const sssp_rounds_ctx* ctx, sssp_rounds_stats* 
  *  kind 2: grid*block lanes each do ops_per_lane atomicAdd on the single
  *          uint64 d_a[0] (16 bytes needed);
  *  kind 3: like kind 2 but one lane per wave (the leader-lane pattern);
- *  kind 4: one lane per wave, ops_per_lane agent-scope loads of d_a[0].
+ *  kind 4: one lane per wave, ops_per_lane agent-scope loads of d_a[0];
+ *  kind 5: grid*block lanes each do ops_per_lane (multiple of 8)
+ *          agent-scope 64-bit loads at random words of the table d_a of
+ *          `size` words (power of two), 8 in flight; d_b: 8 bytes of scratch;
+ *  kind 6 / 7: latency: every lane runs a dependent chain of ops_per_lane
+ *          agent-scope loads (6) or returning atomicMins that leave the
+ *          word unchanged (7) at random words of the table d_a of `size`
+ *          words (power of two); d_b: 8 bytes of scratch.
  * *h_ms receives the kernel time. */
 bq_status bq_probe(int32_t kind, void* d_a, void* d_b, uint64_t size, uint64_t ops_per_lane,
                    int32_t grid, int32_t block, double* h_ms, void* stream);

@@ -1,8 +1,10 @@
-// Roofline probes for the two resources the queue-driven solver uses:
-// HBM bandwidth (a streaming copy, also the calibration kernel for the HBM
-// byte counters) and the device's 64-bit atomic rate (random atomicMin over
-// a table, and atomicAdd on a single contended word).
+// Roofline probes for the resources the queue-driven solver uses: HBM
+// bandwidth (a streaming copy, also the calibration kernel for the HBM byte
+// counters), the device's 64-bit atomic rate (random atomicMin over a table,
+// and atomicAdd on a single contended word) and its rate of random coherent
+// 64-bit loads (the solver's key checks).
 #include <hip/hip_runtime.h>
+#include <limits.h>
 
 #include "host_common.hpp"
 
@@ -64,6 +66,52 @@ __global__ void k_probe_atomic_add1_leader(unsigned long long* word,
     if (acc == 1ull) word[1] = acc;
 }
 
+// ops_per_lane agent-scope 64-bit loads at uniformly random words of a table
+// of 2^log_slots words, 8 in flight per lane (the solver's check before the
+// atomic: a coherent load of a random key)
+__global__ void k_probe_load_rand(const long long* table, unsigned log_slots,
+                                  unsigned long long ops_per_lane, unsigned long long seed,
+                                  unsigned long long* sink) {
+    const unsigned long long tid = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long mask = (1ull << log_slots) - 1ull;
+    long long acc = 0;
+    for (unsigned long long i = 0; i < ops_per_lane; i += 8) {
+        long long o[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const unsigned long long h = mix64(seed ^ (tid * 0x100000001B3ull + i + r));
+            o[r] = __hip_atomic_load(&table[h & mask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) acc += o[r];
+    }
+    if (acc == 0x123456789ll) sink[0] = 1;  // keep the results live
+}
+
+// latency: each lane runs a dependent chain of ops_per_lane operations at
+// random words of a table of 2^log_slots words (the next address depends on
+// the last result); mode 0 agent-scope loads, mode 1 returning atomicMins
+// whose value never changes the word (so the table stays as initialized)
+__global__ void k_probe_chain(long long* table, unsigned log_slots,
+                              unsigned long long ops_per_lane, unsigned mode,
+                              unsigned long long* sink) {
+    const unsigned long long tid = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long mask = (1ull << log_slots) - 1ull;
+    unsigned long long x = mix64(tid);
+    long long acc = 0;
+    for (unsigned long long i = 0; i < ops_per_lane; ++i) {
+        long long v;
+        if (mode == 0)
+            v = __hip_atomic_load(&table[x & mask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            v = __hip_atomic_fetch_min(&table[x & mask], LLONG_MAX, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        acc += v;
+        x = mix64(x ^ (unsigned long long)v);
+    }
+    if (acc == 0x123456789ll) sink[0] = 1;  // keep the results live
+}
+
 // one lane per wave: ops_per_lane agent-scope loads of one word
 __global__ void k_probe_load1_leader(unsigned long long* word, unsigned long long ops_per_lane) {
     if ((threadIdx.x & 63u) != 0u) return;
@@ -111,6 +159,23 @@ bq_status bq_probe(int32_t kind, void* d_a, void* d_b, uint64_t size, uint64_t o
             hipLaunchKernelGGL(k_probe_load1_leader, dim3(grid), dim3(block), 0, s,
                                (unsigned long long*)d_a, (unsigned long long)ops_per_lane);
             break;
+        case 5: {  // random agent-scope loads over a table of size (power of two) words
+            if (!d_b || size < 2 || (size & (size - 1)) || (ops_per_lane & 7ull)) return BQ_EINVAL;
+            unsigned lg = bqh::log2_exact(size);
+            hipLaunchKernelGGL(k_probe_load_rand, dim3(grid), dim3(block), 0, s,
+                               (const long long*)d_a, lg, (unsigned long long)ops_per_lane,
+                               0x5EEDull, (unsigned long long*)d_b);
+            break;
+        }
+        case 6:    // latency chains of agent-scope loads (see k_probe_chain)
+        case 7: {  // latency chains of returning atomicMins
+            if (!d_b || size < 2 || (size & (size - 1))) return BQ_EINVAL;
+            unsigned lg = bqh::log2_exact(size);
+            hipLaunchKernelGGL(k_probe_chain, dim3(grid), dim3(block), 0, s, (long long*)d_a, lg,
+                               (unsigned long long)ops_per_lane, (unsigned)(kind - 6),
+                               (unsigned long long*)d_b);
+            break;
+        }
         default:
             return BQ_EINVAL;
     }

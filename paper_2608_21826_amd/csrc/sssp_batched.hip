@@ -125,10 +125,10 @@ template <int B>
 __global__ __launch_bounds__(SOLVE_WG, SSSP_MIN_WAVES) void k_bsolve(const InstDesc* __restrict__ D, int count,
                                                      const int* claim, int n_claim,
                                                      BatchCtl* bc) {
-    __shared__ WaveLds<B> lds[WAVES_PER_WG];
+    __shared__ WaveLds<B, false> lds[WAVES_PER_WG];
     __shared__ WgShared S;
     __shared__ int s_inst;
-    WaveLds<B>& L = lds[threadIdx.x >> 6];
+    WaveLds<B, false>& L = lds[threadIdx.x >> 6];
     const int wid = (int)(threadIdx.x >> 6);
     WaveStats st{};
     int help = (int)(blockIdx.x % (unsigned)count);

@@ -151,7 +151,13 @@ __device__ __forceinline__ long long pack_key(long long d, unsigned parent, unsi
 // ---------------------------------------------------------------------------
 // the persistent solver
 // ---------------------------------------------------------------------------
-template <int B>
+// edges of one batch that the edge -> item map covers (bytes per wave);
+// MAP = false leaves the map out (the batched solver: its batches are short
+// and it keeps the smaller LDS footprint)
+template <int B, bool MAP>
+constexpr int own_cap() { return MAP ? (B <= 128 ? 8192 : 4096) : 0; }
+
+template <int B, bool MAP = true>
 struct WaveLds {
     unsigned item[B];
     int u[B];
@@ -161,7 +167,55 @@ struct WaveLds {
     unsigned out[OUTCAP];  // improved vertices to publish
     unsigned hv[OUTCAP];   // the ones with long rows, for the chunk lane
     int fanpre[65];
+    alignas(4) unsigned char own[MAP ? own_cap<B, MAP>() : 4];  // batch edge t -> its item
 };
+
+// Fill L.own[0, total) with the item each of the batch's first `total`
+// edges belongs to: mark every non-empty item's first edge, then carry the
+// last mark forward (the marks grow with the position, so it is a running
+// maximum), 4 bytes per lane and a wave max-scan per 256 edges. A lookup is
+// then one LDS byte read instead of a binary search over the item prefix
+// (six dependent reads).
+template <class LDS>
+__device__ void build_edge_map(LDS& L, unsigned e, int total) {
+    const int lane = bq::lane_id();
+    unsigned* own32 = reinterpret_cast<unsigned*>(L.own);
+    const int words = (total + 3) >> 2;
+    for (int i = lane; i < words; i += 64) own32[i] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    for (unsigned c0 = 0; c0 < e; c0 += 64) {
+        const unsigned i = c0 + lane;
+        if (i < e && L.pre[i + 1] > L.pre[i] && L.pre[i] < total)
+            L.own[L.pre[i]] = (unsigned char)i;
+    }
+    __builtin_amdgcn_wave_barrier();
+    unsigned carry = 0;
+    for (int w0 = 0; w0 < words; w0 += 64) {
+        const int wi = w0 + lane;
+        const unsigned v = wi < words ? own32[wi] : 0u;
+        unsigned b0 = v & 255u, b1 = (v >> 8) & 255u, b2 = (v >> 16) & 255u, b3 = v >> 24;
+        b1 = b1 > b0 ? b1 : b0;
+        b2 = b2 > b1 ? b2 : b1;
+        b3 = b3 > b2 ? b3 : b2;
+        unsigned incl = b3;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned y = (unsigned)__shfl_up((int)incl, off, 64);
+            if (lane >= off) incl = y > incl ? y : incl;
+        }
+        unsigned prev = (unsigned)__shfl_up((int)incl, 1, 64);
+        if (lane == 0) prev = 0u;
+        prev = prev > carry ? prev : carry;
+        b0 = b0 > prev ? b0 : prev;
+        b1 = b1 > prev ? b1 : prev;
+        b2 = b2 > prev ? b2 : prev;
+        b3 = b3 > prev ? b3 : prev;
+        if (wi < words) own32[wi] = b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+        const unsigned last = (unsigned)__shfl((int)incl, 63, 64);
+        carry = last > carry ? last : carry;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
 
 // Publish `cnt` items from the wave's LDS buffer `buf` into queue `seg`
 // (Alg. 1 ENQUEUE for all of them at once). The wave's debt (retired items
@@ -428,8 +482,8 @@ __device__ inline void flush_stats(bq::Word* stats, WaveStats& st) {
 // stage it, scan its edges, publish improved vertices; until the query's
 // pending work is 0 (returns 1) or it is stopped (returns -1). The whole
 // workgroup works on the same query; S must be fresh for it.
-template <int B>
-__device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, int wid,
+template <int B, bool MAP>
+__device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& S, int wid,
                               WaveStats& st) {
     const Queue& q = a.q;
     const int lane = bq::lane_id();
@@ -678,6 +732,14 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, in
         // high in-degree targets the atomics would otherwise serialize.
         const int total = carry;
         st.relax += (unsigned long long)total;
+        // edges [0, mapped) find their item in the map, any later ones by a
+        // binary search; a batch that fits one step searches (the map would
+        // cost more than it saves)
+        constexpr int cap = own_cap<B, MAP>();
+        const int mapped = (!MAP || total <= 64 * U) ? 0 : (total < cap ? total : cap);
+        if constexpr (MAP) {
+            if (mapped > 0) build_edge_map(L, e, mapped);
+        }
         int nout = 0;
         int av[U], aw[U], aidx[U];           // group g+2: target, weight, item
         int bv[U], bw[U], bidx[U];           // group g+1
@@ -690,7 +752,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B>& L, WgShared& S, in
                 aw[r] = 0;
                 aidx[r] = 0;
                 if (t < total) {
-                    const int idx = find_item(L.pre, (int)e, t);
+                    const int idx = t < mapped ? (int)L.own[t] : find_item(L.pre, (int)e, t);
                     const long long edge = L.eb[idx] + (t - L.pre[idx]);
                     aidx[r] = idx;
                     av[r] = a.col[edge];
