@@ -350,7 +350,12 @@ bq_status sssp_rounds_last_stats(const sssp_rounds_ctx* ctx, sssp_rounds_stats* 
  *  kind 6 / 7: latency: every lane runs a dependent chain of ops_per_lane
  *          agent-scope loads (6) or returning atomicMins that leave the
  *          word unchanged (7) at random words of the table d_a of `size`
- *          words (power of two); d_b: 8 bytes of scratch.
+ *          words (power of two); d_b: 8 bytes of scratch;
+ *  kind 8: the wave primitives the kernels use, on the int32 d_a[size]
+ *          (size = grid * block, block a multiple of 64): per input i,
+ *          d_b[4i .. 4i+3] = inclusive sum scan, inclusive unsigned max scan,
+ *          the value of the lane below (0 for lane 0) and the value of lane
+ *          63, each over the input's wave of 64.
  * *h_ms receives the kernel time. */
 bq_status bq_probe(int32_t kind, void* d_a, void* d_b, uint64_t size, uint64_t ops_per_lane,
                    int32_t grid, int32_t block, double* h_ms, void* stream);

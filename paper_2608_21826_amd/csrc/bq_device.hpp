@@ -79,14 +79,45 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long x) {
 
 // inclusive wave prefix sum of a 32-bit value (Hillis-Steele over wave64)
 __device__ __forceinline__ int wave_incl_scan(int x) {
-    const int l = lane_id();
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int y = __shfl_up(x, off, 64);
-        if (l >= off) x += y;
-    }
+    // DPP, no LDS: lanes add the lane 1, 2, 4, 8 below them within their row
+    // of 16 (lanes shifted in from outside the row read 0), then row 1 and 3
+    // add the last lane of the row before, and rows 2 and 3 the last lane
+    // of row 1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
     return x;
 }
+
+// inclusive wave maximum scan of an unsigned value (same DPP steps; 0 is the
+// identity)
+__device__ __forceinline__ unsigned wave_incl_max(unsigned x) {
+    unsigned y;
+    y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+    x = y > x ? y : x;
+    y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+    x = y > x ? y : x;
+    y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+    x = y > x ? y : x;
+    y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+    x = y > x ? y : x;
+    y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+    x = y > x ? y : x;
+    y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+    x = y > x ? y : x;
+    return x;
+}
+
+// the value of the lane below (lane 0 reads 0): DPP wave_shr:1
+__device__ __forceinline__ unsigned wave_shr1(unsigned x) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x138, 0xf, 0xf, false);
+}
+
+// the value of lane 63
+__device__ __forceinline__ int lane63(int x) { return __builtin_amdgcn_readlane(x, 63); }
 
 // relaxed agent-scope atomics; P is a pointer in any address space
 template <class P>

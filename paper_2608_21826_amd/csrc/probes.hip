@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <limits.h>
 
+#include "bq_device.hpp"
 #include "host_common.hpp"
 
 namespace {
@@ -112,6 +113,19 @@ __global__ void k_probe_chain(long long* table, unsigned log_slots,
     if (acc == 0x123456789ll) sink[0] = 1;  // keep the results live
 }
 
+// the wave primitives on n = grid * block inputs, over each wave's 64:
+// out[4i] = inclusive sum scan, out[4i+1] = inclusive max scan (unsigned),
+// out[4i+2] = the value of the lane below (0 for lane 0), out[4i+3] = the
+// value of lane 63
+__global__ void k_probe_wave_scan(const int* in, int* out) {
+    const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int x = in[i];
+    out[4 * i] = bq::wave_incl_scan(x);
+    out[4 * i + 1] = (int)bq::wave_incl_max((unsigned)x);
+    out[4 * i + 2] = (int)bq::wave_shr1((unsigned)x);
+    out[4 * i + 3] = bq::lane63(x);
+}
+
 // one lane per wave: ops_per_lane agent-scope loads of one word
 __global__ void k_probe_load1_leader(unsigned long long* word, unsigned long long ops_per_lane) {
     if ((threadIdx.x & 63u) != 0u) return;
@@ -167,6 +181,11 @@ bq_status bq_probe(int32_t kind, void* d_a, void* d_b, uint64_t size, uint64_t o
                                0x5EEDull, (unsigned long long*)d_b);
             break;
         }
+        case 8:  // wave primitives: d_a int32[size] in, d_b int32[4 * size] out
+            if (!d_b || size != (uint64_t)grid * (uint64_t)block || (block & 63)) return BQ_EINVAL;
+            hipLaunchKernelGGL(k_probe_wave_scan, dim3(grid), dim3(block), 0, s, (const int*)d_a,
+                               (int*)d_b);
+            break;
         case 6:    // latency chains of agent-scope loads (see k_probe_chain)
         case 7: {  // latency chains of returning atomicMins
             if (!d_b || size < 2 || (size & (size - 1))) return BQ_EINVAL;

@@ -173,8 +173,8 @@ struct WaveLds {
 // Fill L.own[0, total) with the item each of the batch's first `total`
 // edges belongs to: mark every non-empty item's first edge, then carry the
 // last mark forward (the marks grow with the position, so it is a running
-// maximum), 4 bytes per lane and a wave max-scan per 256 edges. A lookup is
-// then one LDS byte read instead of a binary search over the item prefix
+// maximum), 4 bytes per lane and a DPP wave max-scan per 256 edges. A lookup
+// is then one LDS byte read instead of a binary search over the item prefix
 // (six dependent reads).
 template <class LDS>
 __device__ void build_edge_map(LDS& L, unsigned e, int total) {
@@ -197,21 +197,15 @@ __device__ void build_edge_map(LDS& L, unsigned e, int total) {
         b1 = b1 > b0 ? b1 : b0;
         b2 = b2 > b1 ? b2 : b1;
         b3 = b3 > b2 ? b3 : b2;
-        unsigned incl = b3;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const unsigned y = (unsigned)__shfl_up((int)incl, off, 64);
-            if (lane >= off) incl = y > incl ? y : incl;
-        }
-        unsigned prev = (unsigned)__shfl_up((int)incl, 1, 64);
-        if (lane == 0) prev = 0u;
+        const unsigned incl = bq::wave_incl_max(b3);
+        unsigned prev = bq::wave_shr1(incl);  // lane 0 reads 0
         prev = prev > carry ? prev : carry;
         b0 = b0 > prev ? b0 : prev;
         b1 = b1 > prev ? b1 : prev;
         b2 = b2 > prev ? b2 : prev;
         b3 = b3 > prev ? b3 : prev;
         if (wi < words) own32[wi] = b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
-        const unsigned last = (unsigned)__shfl((int)incl, 63, 64);
+        const unsigned last = (unsigned)bq::lane63((int)incl);
         carry = last > carry ? last : carry;
     }
     __builtin_amdgcn_wave_barrier();
@@ -678,11 +672,11 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
             }
             const int incl = bq::wave_incl_scan(cnt);
             if (i < e) L.pre[i + 1] = carry + incl;
-            carry += __shfl(incl, 63, 64);
+            carry += bq::lane63(incl);
             // fan-out of this 64-item slice: lanes with hubs publish the later
             // chunks of their rows
             const int fincl = bq::wave_incl_scan(fan);
-            const int ftot = __shfl(fincl, 63, 64);
+            const int ftot = bq::lane63(fincl);
             if (ftot > 0) {
                 L.fanpre[lane + 1] = fincl;
                 if (lane == 0) L.fanpre[0] = 0;
