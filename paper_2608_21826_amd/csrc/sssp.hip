@@ -78,14 +78,15 @@ int grid_for(int n_items) {
 }
 
 // Default workgroup count when the caller gives none: about one workgroup
-// (4 waves) per 16K units of n + m/16, a power of two between 4 and the
+// (2 waves) per 8K units of n + m/16, a power of two between 4 and the
 // co-resident maximum. More waves than the work can feed only add traffic on
 // the queue's hot lines and extra relaxations (labels scanned before they
 // settle); sssp_autotune measures instead of guessing.
 int default_grid(int n, long long m, int max_grid) {
+    // one two-wave workgroup per 8K units of n + m/16
     const unsigned long long units = (unsigned long long)n + (unsigned long long)m / 16ull;
     int g = 4;
-    while ((unsigned long long)g * 2ull * 16384ull <= units && g * 2 <= max_grid) g *= 2;
+    while ((unsigned long long)g * 2ull * 8192ull <= units && g * 2 <= max_grid) g *= 2;
     return g < max_grid ? g : max_grid;
 }
 
@@ -94,7 +95,7 @@ template <int B>
 bq_status solve_max_grid(sssp_ctx* c, int slot, int* out) {
     int& per_cu = c->solve_per_cu[slot];
     if (per_cu == 0) {
-        BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<B>, SOLVE_WG, 0));
+        BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<B>, SOLVE_WG_ONE, 0));
         if (per_cu < 1) per_cu = 1;
     }
     *out = per_cu * bqh::device_cus();
@@ -111,9 +112,9 @@ bq_status max_grid_for(sssp_ctx* c, int batch, int* out) {
 
 bq_status launch_solve(const SolveArgs& args, int batch, int grid, hipStream_t s) {
     switch (batch) {
-        case 1: hipLaunchKernelGGL(k_solve<64>, dim3(grid), dim3(SOLVE_WG), 0, s, args); break;
-        case 2: hipLaunchKernelGGL(k_solve<128>, dim3(grid), dim3(SOLVE_WG), 0, s, args); break;
-        default: hipLaunchKernelGGL(k_solve<256>, dim3(grid), dim3(SOLVE_WG), 0, s, args); break;
+        case 1: hipLaunchKernelGGL(k_solve<64>, dim3(grid), dim3(SOLVE_WG_ONE), 0, s, args); break;
+        case 2: hipLaunchKernelGGL(k_solve<128>, dim3(grid), dim3(SOLVE_WG_ONE), 0, s, args); break;
+        default: hipLaunchKernelGGL(k_solve<256>, dim3(grid), dim3(SOLVE_WG_ONE), 0, s, args); break;
     }
     BQ_HIP_TRY(hipGetLastError());
     return BQ_OK;
@@ -451,7 +452,7 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     c->last.ms = ms;
     c->last.solve_ms = sms;
     c->last.grid = grid;
-    c->last.wg_size = SOLVE_WG;
+    c->last.wg_size = SOLVE_WG_ONE;
     const unsigned long long err = h->error.v;
     const bool neg = h->negcycle.v != 0ull;
     if (err != 0ull || h->abort.v != 0ull) c->dirty = true;  // queue not quiescent

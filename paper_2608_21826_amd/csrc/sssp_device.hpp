@@ -94,8 +94,13 @@ constexpr long long KEY_INF = 0x7FFFFFFFFFFFFFFELL;  // d = max, parent = all on
 constexpr long long KEY_NEG = LLONG_MIN | 1ll;
 
 __device__ __forceinline__ bool is_neg_key(long long k) { return k <= KEY_NEG; }
-constexpr int SOLVE_WG = 256;
+constexpr int SOLVE_WG = 256;                 // batched solver workgroup
 constexpr int WAVES_PER_WG = SOLVE_WG / 64;
+// single-query solver workgroup: two waves, so that the few hundred waves a
+// query can feed spread over every CU (and its vector-memory pipeline)
+// instead of filling half of them
+constexpr int SOLVE_WG_ONE = 128;
+constexpr int WAVES_PER_WG_ONE = SOLVE_WG_ONE / 64;
 constexpr int OUTCAP = 1024;  // LDS push buffer per wave
 #ifndef SSSP_UNROLL
 #define SSSP_UNROLL 8

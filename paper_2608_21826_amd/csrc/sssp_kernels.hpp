@@ -70,8 +70,8 @@ __global__ __launch_bounds__(INIT_WG) void k_init(Queue q, long long* key, int n
 }
 
 template <int B>
-__global__ __launch_bounds__(SOLVE_WG, SSSP_MIN_WAVES) void k_solve(SolveArgs a) {
-    __shared__ WaveLds<B> lds[WAVES_PER_WG];
+__global__ __launch_bounds__(SOLVE_WG_ONE, SSSP_MIN_WAVES) void k_solve(SolveArgs a) {
+    __shared__ WaveLds<B> lds[WAVES_PER_WG_ONE];
     __shared__ WgShared S;
     WaveLds<B>& L = lds[threadIdx.x >> 6];
     const int wid = (int)(threadIdx.x >> 6);
