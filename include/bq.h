@@ -443,6 +443,8 @@ typedef struct {
     int32_t status;           /* bq_status of the request: BQ_EINVAL / BQ_EBUSY if
                                  rejected, BQ_EHIP if its upload failed, else the
                                  status of its batched launch */
+    int32_t lane;             /* lane whose launch ran it, -1 if it never ran */
+    int32_t reserved_;
 } bq_response;
 
 typedef struct {
@@ -463,6 +465,16 @@ bq_status bq_server_create(int32_t lanes, int32_t max_batch, int64_t max_batch_n
                            int64_t max_batch_m, int64_t arena_bytes, const bq_launch* launch,
                            bq_server** out);
 bq_status bq_server_destroy(bq_server* s);
+
+/* Reserve the last k lanes (0 <= k < lanes; 0 at creation) for small
+ * requests, those with work for fewer than 64 workgroups
+ * ((n + m/16) / 16384 < 64). A large request is launched alone on one of the
+ * other lanes and, at the front of the arrival order, holds those lanes to
+ * itself; a reserved lane passes over it, so small requests that arrive
+ * behind large ones still start as soon as a reserved lane is free. The
+ * price: large requests have k lanes fewer. BQ_EINVAL for k out of range;
+ * no device work. */
+bq_status bq_server_set_small_lanes(bq_server* s, int32_t k);
 
 /* Register a resident graph (device CSR owned by the caller, kept valid
  * while the server lives); returns its id. */

@@ -33,7 +33,7 @@ EXPORTS = [
     "sssp_last_trace", "sssp_autotune", "sssp_batch_create", "sssp_batch_destroy",
     "sssp_bf_batched", "sssp_batch_last_stats", "sssp_batch_autotune",
     "sssp_bf_batched_start", "sssp_batch_finish", "bq_server_create", "bq_server_destroy",
-    "bq_server_add_graph", "bq_server_run", "bq_arena_create", "bq_arena_destroy",
+    "bq_server_set_small_lanes", "bq_server_add_graph", "bq_server_run", "bq_arena_create", "bq_arena_destroy",
     "bq_arena_alloc", "bq_arena_free", "bq_arena_usage",
     "bq_strerror", "bq_device_cus", "bq_probe",
     "sssp_rounds_create", "sssp_rounds_destroy", "sssp_bf_rounds", "sssp_rounds_last_stats",
@@ -99,7 +99,8 @@ class Request(ctypes.Structure):
 class Response(ctypes.Structure):
     _fields_ = [("latency_us", ctypes.c_double), ("wait_us", ctypes.c_double),
                 ("service_us", ctypes.c_double), ("reached_edges", ctypes.c_int64),
-                ("neg_cycle", ctypes.c_int32), ("status", ctypes.c_int32)]
+                ("neg_cycle", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("lane", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -153,6 +154,7 @@ def lib(path: str | None = None):
         "sssp_batch_finish": ([vp, P(i32), P(i64), i32], i32),
         "bq_server_create": ([i32, i32, i64, i64, i64, P(Launch), P(vp)], i32),
         "bq_server_destroy": ([vp], i32),
+        "bq_server_set_small_lanes": ([vp, i32], i32),
         "bq_server_add_graph": ([vp, i32, i64, vp, vp, vp, P(i32)], i32),
         "bq_server_run": ([vp, i32, P(Request), P(Response), P(ServerStats)], i32),
         "bq_arena_create": ([u64, u64, P(vp)], i32),
@@ -447,16 +449,20 @@ class SsspBatch:
 
 class Server:
     """bq_server: resident graphs, admission by arena memory, continuous
-    batching over `lanes` streams."""
+    batching over `lanes` streams; the last `small_lanes` of them take only
+    small requests."""
 
     def __init__(self, lanes: int, max_batch: int, max_batch_n: int, max_batch_m: int,
-                 arena_bytes: int, launch=None):
+                 arena_bytes: int, launch=None, small_lanes: int = 0):
         h = ctypes.c_void_p()
         _check(lib().bq_server_create(int(lanes), int(max_batch), int(max_batch_n),
                                       int(max_batch_m), int(arena_bytes), _launch(launch),
                                       ctypes.byref(h)), "bq_server_create")
         self.handle = h
         self._graphs = []
+        if small_lanes:
+            _check(lib().bq_server_set_small_lanes(h, int(small_lanes)),
+                   "bq_server_set_small_lanes")
 
     def close(self):
         if self.handle:

@@ -14,7 +14,10 @@
 //   launches run are picked up by the next free lane, so their work overlaps
 //   on the device. Large requests (enough work for 64 or more workgroups)
 //   go alone, so they run with all queue segments and small requests are
-//   not held back until a large one in their batch finishes.
+//   not held back until a large one in their batch finishes. The last k
+//   lanes may be reserved for small requests: a large request at the front
+//   of the arrival order holds every lane it can use, and without a reserved
+//   lane the small requests behind it wait for it to be launched.
 // - Latency = arrival (trace time) to the moment the engine sees the launch
 //   complete; the loop runs on the calling thread with a steady clock.
 #include <hip/hip_runtime.h>
@@ -152,6 +155,7 @@ uint64_t upload_bytes(int32_t n, int64_t m) {
 struct bq_server {
     int device;
     int max_batch;
+    int small_lanes;  // the last small_lanes lanes take only small requests
     int64_t max_batch_n, max_batch_m;
     bq_launch launch;
     std::vector<Lane> lanes;
@@ -175,6 +179,7 @@ bq_status bq_server_create(int32_t lanes, int32_t max_batch, int64_t max_batch_n
     bq_server* s = new bq_server();
     BQ_HIP_TRY(hipGetDevice(&s->device));
     s->max_batch = max_batch;
+    s->small_lanes = 0;
     s->max_batch_n = max_batch_n;
     s->max_batch_m = max_batch_m;
     s->launch = launch ? *launch : bq_launch{};
@@ -218,6 +223,12 @@ bq_status bq_server_destroy(bq_server* s) {
     return BQ_OK;
 }
 
+bq_status bq_server_set_small_lanes(bq_server* s, int32_t k) {
+    if (!s || k < 0 || k >= (int32_t)s->lanes.size()) return BQ_EINVAL;
+    s->small_lanes = k;
+    return BQ_OK;
+}
+
 bq_status bq_server_add_graph(bq_server* s, int32_t n, int64_t m, const int64_t* d_offsets,
                               const int32_t* d_cols, const int32_t* d_w, int32_t* graph_id) {
     if (!s || !graph_id || n < 1 || m < 0 || !d_offsets || (m > 0 && (!d_cols || !d_w)))
@@ -247,6 +258,7 @@ bq_status bq_server_run(bq_server* s, int32_t count, const bq_request* reqs,
         const bq_request& r = reqs[i];
         memset(&resp[i], 0, sizeof(bq_response));
         resp[i].status = BQ_OK;
+        resp[i].lane = -1;
         Need nd{0, 0, 0};
         if (r.graph >= 0) {
             if (r.graph >= (int32_t)s->graphs.size()) {
@@ -315,7 +327,10 @@ bq_status bq_server_run(bq_server* s, int32_t count, const bq_request* reqs,
             progress = true;
         }
         // launches: every free lane takes what has arrived and fits
-        for (auto& L : s->lanes) {
+        const std::size_t first_small = s->lanes.size() - (std::size_t)s->small_lanes;
+        for (std::size_t li = 0; li < s->lanes.size(); ++li) {
+            Lane& L = s->lanes[li];
+            const bool small_only = li >= first_small;
             if (L.busy || pending.empty()) continue;
             inst.clear();
             L.reqs.clear();
@@ -325,13 +340,14 @@ bq_status bq_server_run(bq_server* s, int32_t count, const bq_request* reqs,
             // more workgroups on its own) is launched alone, so it runs with the
             // whole queue-segment set and small requests do not wait for it;
             // small requests are batched together in arrival order, passing
-            // over large ones, which keep their place at the front
+            // over large ones, which keep their place at the front; a lane
+            // reserved for small requests passes over every large one
             std::size_t scan = 0;
             while (scan < pending.size() && (int)L.reqs.size() < s->max_batch) {
                 const int i = pending[scan];
                 const Need& nd = need[i];
                 const bool large = ((long long)nd.n + nd.m / 16) / 16384 >= LARGE_WGS;
-                if (large && !L.reqs.empty()) {
+                if (large && (small_only || !L.reqs.empty())) {
                     ++scan;
                     continue;
                 }
@@ -419,6 +435,7 @@ bq_status bq_server_run(bq_server* s, int32_t count, const bq_request* reqs,
                 L.blocks.clear();
                 continue;
             }
+            for (int i : L.reqs) resp[i].lane = (int32_t)li;
             L.t_launch = now_us();
             L.busy = true;
             ++batches;

@@ -46,3 +46,38 @@ def test_no_cpu_fallback_when_library_missing(tmp_path):
     import paper_2608_21826_amd as pkg
     with pytest.raises(ImportError):
         pkg.lib(str(tmp_path / "missing.so"))
+
+
+STRUCTS = [("Launch", "bq_launch"), ("BenchStats", "bq_bench_stats"), ("SsspStats", "sssp_stats"),
+           ("RoundsStats", "sssp_rounds_stats"), ("Instance", "sssp_instance"),
+           ("Request", "bq_request"), ("Response", "bq_response"),
+           ("ServerStats", "bq_server_stats")]
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes mirrors have the size and field offsets of the
+    header's structs, as a C compiler lays them out."""
+    import shutil
+    import subprocess
+    import paper_2608_21826_amd as pkg
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bq.h"', "int main(void) {"]
+    want = []
+    for py, c in STRUCTS:
+        cls = getattr(pkg, py)
+        lines.append(f'printf("%zu\\n", sizeof({c}));')
+        want.append(ctypes.sizeof(cls))
+        for name, _ in cls._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({c}, {name}));')
+            want.append(getattr(cls, name).offset)
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == want

@@ -84,3 +84,9 @@ def test_random_against_model(seed):
         assert u == used and p == peak
         assert lf == max([l for _, l in m.free], default=0)
     a.close()
+
+
+def test_small_lane_setting_rejects_a_missing_server():
+    """Host-side argument check of the reserved-lane setting (no device)."""
+    assert pkg.lib().bq_server_set_small_lanes(None, 0) == pkg.BQ_EINVAL
+    assert pkg.lib().bq_server_set_small_lanes(None, 1) == pkg.BQ_EINVAL

@@ -176,3 +176,47 @@ def test_large_requests_go_alone(graphs):
     # every large request had a launch of its own; the 9 small ones shared
     assert n_big + 1 <= st["launches"] < len(reqs)
     srv.close()
+
+
+def test_reserved_small_lane(graphs):
+    """With the last lane reserved, large requests queued in front of small
+    ones run only on the other lane, small ones also start on the reserved
+    lane, and every answer is still exact."""
+    resident, uploads = graphs
+    big = synth.rmat(19, 16, seed=12)  # (n + m/16) / 16384 = 64
+    srv = make_server(resident + [big], lanes=2, max_batch=16)
+    # k must leave at least one lane for large requests
+    assert pkg.lib().bq_server_set_small_lanes(srv.handle, 2) == pkg.BQ_EINVAL
+    assert pkg.lib().bq_server_set_small_lanes(srv.handle, -1) == pkg.BQ_EINVAL
+    assert pkg.lib().bq_server_set_small_lanes(srv.handle, 1) == 0
+    rng = np.random.default_rng(14)
+    reqs, truth = [], []
+    for i in range(12):
+        gid = 3 if i < 3 else int(rng.integers(0, 3))
+        g = (resident + [big])[gid]
+        src = int(rng.integers(0, g.n))
+        reqs.append({"arrival_us": 0.0, "src": src, "graph": gid,
+                     "dist": torch.empty(g.n, dtype=torch.int64, device=DEV),
+                     "pred": torch.empty(g.n, dtype=torch.int32, device=DEV)})
+        truth.append((g, src))
+    resp, st = srv.run(reqs)
+    print(f"[served] reserved lane {st} lanes {[x['lane'] for x in resp]}", flush=True)
+    check(reqs, truth, resp)
+    assert all(x["lane"] == 0 for x, r in zip(resp, reqs) if r["graph"] == 3)
+    assert any(x["lane"] == 1 for x, r in zip(resp, reqs) if r["graph"] != 3)
+    assert all(x["lane"] in (0, 1) for x in resp)
+    srv.close()
+
+
+def test_lane_is_reported(graphs):
+    """Every request that ran names the lane of its launch; a rejected one
+    names none."""
+    resident, uploads = graphs
+    srv = make_server(resident, lanes=3)
+    reqs, truth = build_trace(resident, uploads, 20, 40.0, 15)
+    reqs.append({"arrival_us": reqs[-1]["arrival_us"] + 1.0, "src": 0, "graph": 99})
+    resp, st = srv.run(reqs)
+    check(reqs[:-1], truth, resp[:-1])
+    assert all(0 <= x["lane"] < 3 for x in resp[:-1])
+    assert resp[-1]["status"] == pkg.BQ_EINVAL and resp[-1]["lane"] == -1
+    srv.close()
