@@ -207,15 +207,20 @@ def reached_edges(torch, dist, deg_t):
     return int(deg_t[dist != np.iinfo(np.int64).max].sum().item())
 
 
-def batched_leg(pkg, torch, dev, name, queries, graphs, steps, single_launch=None):
+def batched_leg(pkg, torch, dev, name, queries, graphs, steps, single_launch=None,
+                batch_launch=None):
     """One batched launch over all queries vs the same queries one sssp_bf
     call at a time (each a separate synchronous call). Device time from HIP
-    events in both cases; reached edges summed over the queries."""
+    events in both cases; reached edges summed over the queries. The batched
+    launch is autotuned unless batch_launch fixes it."""
     tn = sum(g.n for g in graphs)
     tm = sum(g.m for g in graphs)
     b = pkg.SsspBatch(len(queries), tn, tm)
-    launch, tune_ms = b.autotune(queries)
-    log(f"{name}: batch autotune {launch} {tune_ms:.3f} ms")
+    if batch_launch is None:
+        launch, tune_ms = b.autotune(queries)
+        log(f"{name}: batch autotune {launch} {tune_ms:.3f} ms")
+    else:
+        launch = dict(batch_launch)
     for _ in range(2):
         b.solve(queries, launch=launch, graph=True)
     ms = []
@@ -462,6 +467,11 @@ def main():
                     help="only run the solver policy / workgroup-count sweep")
     ap.add_argument("--no-probes", action="store_true",
                     help="skip the HBM copy and atomic-rate probes (roofline context)")
+    ap.add_argument("--batched-launch", type=str, default=None,
+                    help='fixed launch of the batched legs as JSON (no autotuning), '
+                         'e.g. {"wg_count":512,"ticket_batch":1}')
+    ap.add_argument("--batched-only", choices=("rmat20x64", "er256"), default=None,
+                    help="run only this batched workload (for counter passes on k_bsolve)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU form of "
@@ -648,10 +658,14 @@ def main():
         srcs = synth.random_sources(g, 64, seed=synth.SEED_BASE + 3)
         qs = [(off, col, w, int(sv), torch.empty(g.n, dtype=torch.int64, device=dev),
                torch.empty(g.n, dtype=torch.int32, device=dev)) for sv in srcs]
-        batched["rmat20_x64_sources"] = batched_leg(pkg, torch, dev, "rmat20x64", qs,
-                                                    [g] * len(qs), 5, sssp_launch or None)
-        log(f"batched rmat20x64 {batched['rmat20_x64_sources']}")
+        blaunch = json.loads(args.batched_launch) if args.batched_launch else None
+        if args.batched_only in (None, "rmat20x64"):
+            batched["rmat20_x64_sources"] = batched_leg(pkg, torch, dev, "rmat20x64", qs,
+                                                        [g] * len(qs), 5, sssp_launch or None,
+                                                        blaunch)
+            log(f"batched rmat20x64 {batched['rmat20_x64_sources']}")
         del qs
+    if not args.no_batched and not args.sssp_only and args.batched_only in (None, "er256"):
         t0 = time.time()
         ers = synth.er_batch(256)
         log(f"er256 generated in {time.time() - t0:.1f}s")
@@ -661,9 +675,10 @@ def main():
                        torch.from_numpy(eg.w).to(dev), eg.src,
                        torch.empty(eg.n, dtype=torch.int64, device=dev),
                        torch.empty(eg.n, dtype=torch.int32, device=dev)))
-        batched["er256"] = batched_leg(pkg, torch, dev, "er256", qs, ers, 5)
+        batched["er256"] = batched_leg(pkg, torch, dev, "er256", qs, ers, 5, None, blaunch)
         log(f"batched er256 {batched['er256']}")
         del qs, ers
+    if not args.no_batched and not args.sssp_only:
         out["batched"] = batched
     if args.served_requests > 0 and not args.sssp_only:
         t0 = time.time()

@@ -6,11 +6,14 @@
 //  k_binit   - per "unit" (a slice of one query's vertices and edges): keys,
 //              weight-range partials; a query's first unit also resets its
 //              control block and enqueues its source
-//  k_bsolve  - persistent workgroups claim queries from a claim list (queries
+//  k_bsolve  - persistent workgroups claim queries from claim lists (queries
 //              sorted by size, each listed in proportion to its work, so big
-//              queries get several workgroups) and, when the list runs out,
-//              join any unfinished query; each runs the solver loop of the
-//              single-query launch on that query's queue
+//              queries get several workgroups) and, when their list runs out,
+//              join an unfinished query; each runs the solver loop of the
+//              single-query launch on that query's queue. There is one list
+//              per XCD: a query whose share fits one XCD's workgroups is
+//              listed on one list only, so its keys are cached in one L2
+//              instead of being spread over all eight
 //  k_bunpack - per unit: distances and predecessors; per query: the result
 //              flags
 #include <hip/hip_runtime.h>
@@ -50,8 +53,12 @@ struct Unit {
     long long v0, v1, e0, e1;
 };
 
+// Workgroups are dispatched to the XCDs in turn (workgroup i on XCD i mod 8),
+// so workgroup i claims from list i mod n_lists.
+constexpr int NLIST = 8;
+
 struct BatchCtl {
-    bq::Word cursor;  // next claim-list entry
+    bq::Word cursor[NLIST];  // next entry of each claim list
     bq::Word stats[bq::ST_N];
 };
 
@@ -59,7 +66,7 @@ __global__ __launch_bounds__(BINIT_WG) void k_binit(const InstDesc* D, const Uni
                                                     int n_units, int* partials, BatchCtl* bc,
                                                     unsigned long long* reached) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        bc->cursor.v = 0ull;
+        for (int x = 0; x < NLIST; ++x) bc->cursor[x].v = 0ull;
         for (int i = 0; i < bq::ST_N; ++i) bc->stats[i].v = 0ull;
     }
     __shared__ int slo[BINIT_WG / 64], shi[BINIT_WG / 64];
@@ -122,8 +129,10 @@ template <int B>
 // D is read-only for the whole launch (__restrict__): its uniform loads then
 // go through the scalar cache, and the descriptor of the query a workgroup
 // works on stays in scalar registers instead of taking vector ones.
+// claim: NLIST + 1 list offsets, then the entries (descriptor indices) of
+// list x at [claim[x], claim[x + 1]) after that header.
 __global__ __launch_bounds__(SOLVE_WG, SSSP_MIN_WAVES) void k_bsolve(const InstDesc* __restrict__ D, int count,
-                                                     const int* claim, int n_claim,
+                                                     const int* claim, int n_lists,
                                                      BatchCtl* bc) {
     __shared__ WaveLds<B, false> lds[WAVES_PER_WG];
     __shared__ WgShared S;
@@ -132,13 +141,34 @@ __global__ __launch_bounds__(SOLVE_WG, SSSP_MIN_WAVES) void k_bsolve(const InstD
     const int wid = (int)(threadIdx.x >> 6);
     WaveStats st{};
     int help = (int)(blockIdx.x % (unsigned)count);
+    const int x = (int)(blockIdx.x % (unsigned)n_lists);
+    const int* list = claim + NLIST + 1;
+    const int lo = claim[x], hi = claim[x + 1];
+    bool own = true;
     for (;;) {
         if (threadIdx.x == 0) {
             int i = -1;
-            const unsigned long long c = bq::add_rlx(&bc->cursor.v, 1ull);
-            if (c < (unsigned long long)n_claim) {
-                i = claim[c];
-            } else {
+            if (own) {
+                const unsigned long long c = bq::add_rlx(&bc->cursor[x].v, 1ull);
+                if (c < (unsigned long long)(hi - lo)) i = list[lo + (int)c];
+                else own = false;
+            }
+            if (i < 0 && hi > lo) {
+                // an unfinished query of this list first (its keys are in
+                // this XCD's L2), starting at a place of its own
+                const int len = hi - lo;
+                const int s0 = (int)((blockIdx.x / (unsigned)n_lists) % (unsigned)len);
+                for (int k = 0; k < len; ++k) {
+                    const int e = lo + (s0 + k) % len;
+                    const int j = list[e];
+                    if (k > 0 && e > lo && list[e - 1] == j) continue;  // same query again
+                    if (bq::ld_rlx(&D[j].a.q.ctrl->aux[5].v) == 0ull) {
+                        i = j;
+                        break;
+                    }
+                }
+            }
+            if (i < 0) {
                 for (int k = 0; k < count; ++k) {
                     const int j = (help + k) % count;
                     if (bq::ld_rlx(&D[j].a.q.ctrl->aux[5].v) == 0ull) {
@@ -254,7 +284,7 @@ struct sssp_batch {
 
 namespace {
 
-bq_status batch_launch_kernels(sssp_batch* b, int count, int n_units, int n_claim, int grid,
+bq_status batch_launch_kernels(sssp_batch* b, int count, int n_units, int n_lists, int grid,
                                int B) {
     hipStream_t s = b->stream;
     const int ug = n_units < 2048 ? n_units : 2048;
@@ -263,15 +293,15 @@ bq_status batch_launch_kernels(sssp_batch* b, int count, int n_units, int n_clai
     switch (B) {
         case 64:
             hipLaunchKernelGGL(k_bsolve<64>, dim3(grid), dim3(SOLVE_WG), 0, s, b->d_desc, count,
-                               b->d_claim, n_claim, b->d_bc);
+                               b->d_claim, n_lists, b->d_bc);
             break;
         case 128:
             hipLaunchKernelGGL(k_bsolve<128>, dim3(grid), dim3(SOLVE_WG), 0, s, b->d_desc, count,
-                               b->d_claim, n_claim, b->d_bc);
+                               b->d_claim, n_lists, b->d_bc);
             break;
         default:
             hipLaunchKernelGGL(k_bsolve<256>, dim3(grid), dim3(SOLVE_WG), 0, s, b->d_desc, count,
-                               b->d_claim, n_claim, b->d_bc);
+                               b->d_claim, n_lists, b->d_bc);
             break;
     }
     hipLaunchKernelGGL(k_bunpack, dim3(ug), dim3(256), 0, s, b->d_desc, b->d_units, n_units,
@@ -315,7 +345,7 @@ bq_status sssp_batch_create(int32_t max_instances, int64_t max_total_n, int64_t 
                        (size_t)max_instances * 4096);  // vertex queue + chunk lane
     b->chunk_cap = (size_t)(max_total_m / 64 + max_instances);
     b->max_units = (size_t)((max_total_n + max_total_m) / UNIT + 2 * max_instances);
-    b->max_claim = (size_t)(8 * 4096 + max_instances);
+    b->max_claim = (size_t)(8 * 4096 + max_instances + NLIST + 1);
     if (hipMalloc(&b->slots, sizeof(unsigned long long) * b->slot_cap) != hipSuccess ||
         hipMalloc(&b->chunks, sizeof(unsigned) * b->chunk_cap) != hipSuccess ||
         hipMalloc(&b->ctrls, sizeof(bq::Ctrl) * max_instances * MAX_Q) != hipSuccess ||
@@ -443,12 +473,28 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
     layout.reserve(3 * count + 2);
     size_t slot_off = 0, chunk_off = 0;
     int n_units = 0, n_claim = 0;
+    std::vector<std::vector<int>> lists(NLIST);
+    std::vector<long long> list_work(NLIST, 0);
     long long tot_work = 0;
     for (int i = 0; i < count; ++i) tot_work += work[i];
+    // workgroups per query in proportion to its share of the work (at least
+    // one); a query whose share fits one XCD's workgroups is confined to one
+    // claim list, a bigger one is spread over all lists
+    const int n_lists = grid < NLIST ? grid : NLIST;
+    std::vector<long long> tgts(count);
+    std::vector<char> confined(count);
+    for (int k = 0; k < count; ++k) {
+        long long tgt = tot_work > 0 ? (long long)grid * work[order[k]] / tot_work : 1;
+        if (tgt < 1) tgt = 1;
+        tgts[k] = tgt;
+        confined[k] = n_lists > 1 && tgt * n_lists <= grid;
+    }
     // queue capacity of each query, and its segments: a query that can feed
-    // 16 or more workgroups gets up to MAX_SEG queue segments (one per XCD,
-    // as in the single-query solver) while the slot arena has room left over
-    // after every query's first segment, biggest queries first
+    // 16 or more workgroups and is spread over the XCDs gets up to MAX_SEG
+    // queue segments (one per XCD, as in the single-query solver) while the
+    // slot arena has room left over after every query's first segment,
+    // biggest queries first; a confined query keeps one (its workgroups all
+    // have the same home)
     std::vector<unsigned long long> caps(count);
     std::vector<unsigned> nsegs(count, 1u);
     {
@@ -466,7 +512,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         for (int k = 0; k < count; ++k) {
             const sssp_instance& x = h_inst[order[k]];
             const long long units = (long long)x.n + x.m / 16;
-            if (units / 16384 < 16) continue;
+            if (units / 16384 < 16 || confined[k]) continue;
             unsigned long long extra = spare / (2 * caps[k]);
             if (extra > MAX_SEG - 1) extra = MAX_SEG - 1;
             nsegs[k] = 1u + (unsigned)extra;
@@ -526,16 +572,39 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         }
         n_units += ku;
         d.unit_end = n_units;
-        // workgroups in proportion to the query's share of the work
-        long long tgt = tot_work > 0 ? (long long)grid * work[i] / tot_work : 1;
-        if (tgt < 1) tgt = 1;
-        for (long long t = 0; t < tgt && (size_t)n_claim < b->max_claim; ++t)
-            b->h_claim[n_claim++] = k;
+        // claim entries: biggest queries first (spread ones round the
+        // lists), each confined query on the list with the least work so far
+        if (confined[k]) {
+            int best = 0;
+            for (int l = 1; l < n_lists; ++l)
+                if (list_work[l] < list_work[best]) best = l;
+            for (long long t = 0; t < tgts[k]; ++t) lists[best].push_back(k);
+            list_work[best] += work[i];
+        } else {
+            for (long long t = 0; t < tgts[k]; ++t) {
+                const int l = (int)(t % n_lists);
+                lists[l].push_back(k);
+                list_work[l] += work[i] / tgts[k];
+            }
+        }
         layout.push_back(cap);
         layout.push_back(slot_off);
         layout.push_back(nseg);
         slot_off += 2 * nseg * cap;  // vertex queues and their chunk lanes
         chunk_off += chunks;
+    }
+    // the claim array: list offsets, then the lists one after another
+    {
+        size_t total = NLIST + 1;
+        for (const auto& l : lists) total += l.size();
+        if (total > b->max_claim) return BQ_EBUSY;
+        int pos = 0;
+        for (int l = 0; l < NLIST; ++l) {
+            b->h_claim[l] = pos;
+            for (int e : lists[l]) b->h_claim[NLIST + 1 + pos++] = e;
+        }
+        b->h_claim[NLIST] = pos;
+        n_claim = (int)total;
     }
     hipStream_t cs = bqh::as_stream(stream);
     hipStream_t s = b->stream;
@@ -561,7 +630,8 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
     if (L.flags & BQ_F_GRAPH) {
         const unsigned long long key[8] = {(unsigned long long)count, (unsigned long long)n_units,
                                            (unsigned long long)n_claim, (unsigned long long)grid,
-                                           (unsigned long long)B, 0, 0, 0};
+                                           (unsigned long long)B, (unsigned long long)n_lists,
+                                           0, 0};
         if (!b->exec || memcmp(key, b->graph_key, sizeof key) != 0) {
             if (b->exec) {
                 (void)hipGraphExecDestroy(b->exec);
@@ -572,7 +642,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
                 b->graph = nullptr;
             }
             BQ_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            bq_status st = batch_launch_kernels(b, count, n_units, n_claim, grid, B);
+            bq_status st = batch_launch_kernels(b, count, n_units, n_lists, grid, B);
             hipGraph_t g = nullptr;
             hipError_t ce = hipStreamEndCapture(s, &g);
             if (st != BQ_OK) return st;
@@ -583,7 +653,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         }
         BQ_HIP_TRY(hipGraphLaunch(b->exec, s));
     } else {
-        bq_status st = batch_launch_kernels(b, count, n_units, n_claim, grid, B);
+        bq_status st = batch_launch_kernels(b, count, n_units, n_lists, grid, B);
         if (st != BQ_OK) return st;
     }
     BQ_HIP_TRY(hipEventRecord(b->ev1, s));
