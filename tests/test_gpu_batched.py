@@ -84,6 +84,7 @@ def test_mixed_batch_matches_oracle(batch, seed):
     {"wg_count": 1}, {"wg_count": 3}, {"wg_count": 7, "ticket_batch": 2},
     {"row_chunk": 256}, {"queue_scale": 1}, {"row_chunk": 64, "wg_count": 16},
     {"flags": 8, "wg_count": 5}, {"flags": 8, "ticket_batch": 4},
+    {"wg_count": 9}, {"wg_count": 12, "ticket_batch": 2},
 ])
 def test_launch_shapes(batch, launch):
     print(f"[batched] launch {launch}", flush=True)
@@ -219,3 +220,18 @@ def test_rmat20_64_sources():
     sample = list(range(0, 64, 6))[:12]
     check_all([qs[i] for i in sample], [keep[i] for i in sample], [neg[i] for i in sample])
     b.close()
+
+
+@pytest.mark.parametrize("wgs", [8, 24, 64])
+def test_many_small_queries_on_few_workgroups(batch, wgs):
+    """More queries than workgroups: each XCD's claim list holds several
+    queries, later ones are claimed as earlier ones finish, and workgroups
+    whose list is used up help elsewhere; every answer stays exact."""
+    print(f"[batched] 64 small queries, wg_count={wgs}", flush=True)
+    items = []
+    for i in range(64):
+        g = (synth.erdos_renyi(500 + 97 * i, 8, seed=700 + i) if i % 2 == 0
+             else synth.potential_random(200 + 31 * i, 6 * (200 + 31 * i), seed=700 + i))
+        items.append((g, int(i * 7919 % g.n), upload(g)))
+    qs, keep = make_queries(items)
+    check_all(qs, keep, batch.solve(qs, launch={"wg_count": wgs}))
