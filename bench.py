@@ -259,7 +259,7 @@ def batched_leg(pkg, torch, dev, name, queries, graphs, steps, single_launch=Non
             "launch": launch, "relaxations": int(st["relaxations"])}
 
 
-def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0):
+def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0, lanes=4):
     """Served form (Poisson arrivals over 3 resident graphs + one-off ER
     uploads): the continuous-batching engine vs the same engine limited to
     one query per launch and one lane (sequential one-query launches), at
@@ -325,7 +325,7 @@ def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0):
         qps = load * 1e3 / mean_service_ms
         arr = np.cumsum(rng.exponential(1e6 / qps, size=n_req))
         res[f"qps_{load}x"] = {"qps": round(qps, 2),
-                               "continuous_batching": run(4, 32, arr),
+                               "continuous_batching": run(lanes, 32, arr),
                                "sequential": run(1, 1, arr)}
     return res
 
@@ -461,6 +461,8 @@ def main():
                     help="skip the batched-vs-one-at-a-time legs")
     ap.add_argument("--served-requests", type=int, default=100,
                     help="requests per served run (0 skips the served leg)")
+    ap.add_argument("--served-lanes", type=int, default=4,
+                    help="lanes of the continuous-batching engine in the served leg")
     ap.add_argument("--queue-sweep", action="store_true",
                     help="only run the queue scenario / policy / launch-shape sweep")
     ap.add_argument("--bf-sweep", action="store_true",
@@ -682,7 +684,8 @@ def main():
         out["batched"] = batched
     if args.served_requests > 0 and not args.sssp_only:
         t0 = time.time()
-        out["served"] = served_leg(pkg, torch, dev, g, (off, col, w), args.served_requests)
+        out["served"] = served_leg(pkg, torch, dev, g, (off, col, w), args.served_requests,
+                                   lanes=args.served_lanes)
         log(f"served leg in {time.time() - t0:.1f}s: {out['served']}")
     if not args.no_cpu:
         log("cpu baseline ...")
