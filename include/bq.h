@@ -377,7 +377,10 @@ bq_status sssp_batch_destroy(sssp_batch* b);
  * pred, h_neg_cycle[i]). Queries are ordered by size; persistent workgroups
  * claim them biggest first, each query getting workgroups in proportion to
  * its edges + vertices, and workgroups whose claims are used up join
- * unfinished queries. A query with (n + m/16) / 16384 >= 16 gets up to 8
+ * unfinished queries. Claims come from one list per XCD (workgroup i takes
+ * from list i mod 8): a query whose share fits one XCD's workgroups is
+ * listed on one list only and keeps one queue segment; a bigger query is
+ * spread over all lists, and one with (n + m/16) / 16384 >= 16 gets up to 8
  * queue segments (as sssp_bf) while the workspace's slots allow, biggest
  * first. With BQ_F_GRAPH the init / solve / unpack kernels run
  * as one replayed hipGraph on the batch's own stream (ordered after the
