@@ -62,7 +62,9 @@ typedef struct {
                              sssp_bf and sssp_bf_batched take about one per
                              16K units of n + m/16 (per query, at least one),
                              up to the co-resident maximum */
-    int32_t ticket_batch; /* b: a wave dequeues up to 64*b items per ticket */
+    int32_t ticket_batch; /* b: a wave dequeues up to 64*b items per ticket;
+                             0 = 1; the solvers take 1, 2 or 4 (BQ_EINVAL
+                             otherwise: their LDS staging grows with b) */
     uint32_t flags;       /* BQ_F_* */
     uint64_t timeout_us;  /* watchdog for a single wait; 0 = 2 s. A solve
                              running longer than 10x this is stopped too
