@@ -144,6 +144,92 @@ def cpu_baselines_more(g, m_reached, budget_s=5.0):
     return out
 
 
+def queue_roofline(ms, launch, b1_ms, probes):
+    """Roofline of the Global Mixed queue run (k_bench_mixed).
+
+    Bulk (the timed launch, 64*b items per ticket): 12 algorithmic bytes
+    per operation (4 B payload, 4 B ticket read, 4 B ticket write) against
+    HBM. One ticket per wave (b = 1): the broker count word takes one
+    contended atomic per wave operation, 2^26 / 64 of them at least, and a
+    single word serializes its atomics; the peak is the measured rate of
+    one contended word (probe of leader-lane atomicAdds)."""
+    b = int(launch.get("ticket_batch", 1))
+    bulk = QUEUE_OPS * 12 / (ms * 1e-3) / 1e9
+    res = {"bulk": {"bound": "hbm", "achieved": round(bulk, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(bulk / HBM_PEAK_GBS, 4),
+                    "algorithmic_bytes": QUEUE_OPS * 12, "ticket_batch": b,
+                    "kernel": "k_bench_mixed", "kernel_ms": round(ms, 4)}}
+    word = None
+    if probes:
+        word = probes.get("atomic_add_one_word_leader_Mops_w4096")
+    if b1_ms:
+        atom = (QUEUE_OPS // 64) / (b1_ms * 1e-3) / 1e6
+        res["one_ticket_per_wave"] = {
+            "bound": "contended_atomic", "achieved": round(atom, 1),
+            "peak": word, "unit": "M atomics/s on the count word",
+            "frac": round(atom / word, 4) if word else None,
+            "atomics_on_count_word": QUEUE_OPS // 64, "kernel_ms": round(b1_ms, 3)}
+    return res
+
+
+def cpu_graph_baselines(graphs, budget_s=4.0):
+    """The oracle beside the grid and road legs: its rounds (Alg. 3 on one
+    processing element, 1 core), the sequential FIFO form (1 core) and the
+    Jacobi rounds on all host cores, each repeated for about budget_s (at
+    least once). `graphs`: (label, graph, which of the three to run)."""
+    import oracle
+    out = {}
+
+    def timed(fn):
+        times = []
+        t_all = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
+            r = fn()
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_all > budget_s or len(times) >= 20:
+                return float(np.median(times)), len(times), r
+
+    for label, g, kinds in graphs:
+        d = {}
+        if "rounds" in kinds:
+            t, k, (dist, neg, rounds) = timed(lambda: oracle.bf_rounds(g))
+            mr = int(np.diff(g.offsets)[dist != oracle.INF].sum())
+            d["oracle_rounds_1core"] = {"value": round(mr / t / 1e9, 5), "unit": "GTEPS",
+                                        "cores": 1, "kind": "oracle", "ms": round(t * 1e3, 2),
+                                        "sample": f"{k} full solves, {rounds} rounds each"}
+        if "fifo" in kinds:
+            t, k, (dist, neg, pops, rel) = timed(lambda: oracle.bf_fifo(g))
+            mr = int(np.diff(g.offsets)[dist != oracle.INF].sum())
+            d["fifo_1core"] = {"value": round(mr / t / 1e9, 5), "unit": "GTEPS", "cores": 1,
+                               "kind": "oracle_fifo", "ms": round(t * 1e3, 2),
+                               "sample": f"{k} full solves, k = {rel / max(mr, 1):.1f}"}
+        if "jacobi" in kinds:
+            csc = oracle.transpose(g)
+            t, k, (dist, neg, rounds, threads) = timed(lambda: oracle.bf_jacobi(g, csc))
+            mr = int(np.diff(g.offsets)[dist != oracle.INF].sum())
+            d["jacobi_all_cores"] = {"value": round(mr / t / 1e9, 5), "unit": "GTEPS",
+                                     "cores": threads, "kind": "parallel_rounds",
+                                     "ms": round(t * 1e3, 2),
+                                     "sample": f"{k} full solves, {rounds} Jacobi rounds each"}
+        out[label] = d
+        log(f"cpu {label}: {d}")
+    return out
+
+
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_queue_baselines(threads=None):
     """The queue on the host (bounded samples): a sequential ring on one core
     running the Global Mixed sequence (2^26 operations), and Alg. 1's Broker
@@ -207,8 +293,106 @@ def reached_edges(torch, dist, deg_t):
     return int(deg_t[dist != np.iinfo(np.int64).max].sum().item())
 
 
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def golden(name):
+    """Stored result of a full-size configuration (written by
+    tests/golden/make_golden.py from the CPU oracle and certified there by
+    an independent algorithm)."""
+    fname = {"grid64": "grid64.json", "rmat20": "rmat20.json",
+             "rmat20_x64_sources": "rmat20.json", "road2048": "road2048.json",
+             "road2048_negcycle": "road2048.json"}[name]
+    with open(os.path.join(GOLDEN_DIR, fname)) as f:
+        return json.load(f)[name]
+
+
+def sha256(a) -> str:
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def graph_sha256(g) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for a in (g.offsets, g.cols, g.w):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def matches_golden(rec, dist, pred) -> bool:
+    """dist / pred (device tensors) equal the stored result byte for byte."""
+    return (sha256(dist.cpu().numpy()) == rec["dist_sha256"] and
+            sha256(pred.cpu().numpy()) == rec["pred_sha256"])
+
+
+def graph_leg(pkg, torch, dev, name, g, reps, warmup, launch=None, ctx=None):
+    """Solves of one configuration at a fixed launch (the library default
+    unless given): median device time over `reps` HIP-event-timed solves
+    after `warmup` untimed ones; reached-edge GTEPS; work ratio; every
+    solve's output checked against the stored result (outside the timing)."""
+    rec = golden(name)
+    assert graph_sha256(g) == rec["graph_sha256"], f"{name}: generator output changed"
+    off = torch.from_numpy(g.offsets).to(dev)
+    col = torch.from_numpy(g.cols).to(dev)
+    w = torch.from_numpy(g.w).to(dev)
+    own = ctx is None
+    if own:
+        ctx = pkg.SsspContext(g.n, g.m)
+    dist = torch.empty(g.n, dtype=torch.int64, device=dev)
+    pred = torch.empty(g.n, dtype=torch.int32, device=dev)
+    try:
+        for _ in range(warmup):
+            ctx.solve(off, col, w, g.src, dist=dist, pred=pred, launch=launch)
+        ms, kms, rel, exact = [], [], [], True
+        for _ in range(reps):
+            _, _, neg = ctx.solve(off, col, w, g.src, dist=dist, pred=pred, launch=launch)
+            st = ctx.stats()
+            ms.append(st["ms"])
+            kms.append(st["solve_ms"])
+            rel.append(st["relaxations"])
+            exact &= (not neg) and matches_golden(rec, dist, pred)
+        grid = int(st["grid"])
+    finally:
+        if own:
+            ctx.close()
+    med = float(np.median(ms))
+    mr = rec["m_reached"]
+    return {"ms_median": round(med, 4), "ms_min": round(float(np.min(ms)), 4),
+            "solver_kernel_ms": round(float(np.median(kms)), 4),
+            "gteps": round(mr / (med * 1e-3) / 1e9, 4), "m_reached": mr,
+            "work_ratio_k": round(float(np.mean(rel)) / mr, 3), "grid": grid,
+            "launch": launch or "library default", "runs": reps,
+            "parity": "exact" if exact else "MISMATCH"}
+
+
+def negcycle_leg(pkg, torch, dev, g, reps=3, launch=None):
+    """Detection of the planted negative 3-cycle: device time of the solve
+    until the flag is final (HIP events around init, solve and unpack)."""
+    rec = golden("road2048_negcycle")
+    assert graph_sha256(g) == rec["graph_sha256"], "road2048_negcycle: generator output changed"
+    off = torch.from_numpy(g.offsets).to(dev)
+    col = torch.from_numpy(g.cols).to(dev)
+    w = torch.from_numpy(g.w).to(dev)
+    ctx = pkg.SsspContext(g.n, g.m)
+    try:
+        ms, flags, walks = [], [], []
+        for _ in range(reps):
+            _, _, neg = ctx.solve(off, col, w, g.src, launch=launch)
+            st = ctx.stats()
+            ms.append(st["ms"])
+            flags.append(bool(neg))
+            walks.append(st["walks"])
+    finally:
+        ctx.close()
+    return {"detect_ms_median": round(float(np.median(ms)), 3),
+            "detect_ms_max": round(float(np.max(ms)), 3), "runs": reps,
+            "flag": int(all(flags)), "parity": "exact" if all(flags) == rec["neg_cycle"]
+            else "MISMATCH", "parent_walks": int(np.median(walks))}
+
+
 def batched_leg(pkg, torch, dev, name, queries, graphs, steps, single_launch=None,
-                batch_launch=None):
+                batch_launch=None, check=None):
     """One batched launch over all queries vs the same queries one sssp_bf
     call at a time (each a separate synchronous call). Device time from HIP
     events in both cases; reached edges summed over the queries. The batched
@@ -228,6 +412,8 @@ def batched_leg(pkg, torch, dev, name, queries, graphs, steps, single_launch=Non
         b.solve(queries, launch=launch, graph=True)
         ms.append(b.stats()["ms"])
     st = b.stats()
+    # the batched outputs (before the one-at-a-time solves overwrite them)
+    parity = check(queries) if check is not None else None
     degs = {}
     m_reached = 0
     for (off, col, w, src, dist, pred), g in zip(queries, graphs):
@@ -256,7 +442,8 @@ def batched_leg(pkg, torch, dev, name, queries, graphs, steps, single_launch=Non
             "one_at_a_time_wall_ms": round(one_wall, 3),
             "one_at_a_time_gteps": round(m_reached / float(np.sum(one_ms)) / 1e6, 3),
             "speedup": round(float(np.sum(one_ms)) / bms, 2),
-            "launch": launch, "relaxations": int(st["relaxations"])}
+            "launch": launch, "relaxations": int(st["relaxations"]),
+            **({"parity": parity} if parity is not None else {})}
 
 
 def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0, lanes=4):
@@ -445,7 +632,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baselines")
     ap.add_argument("--calib", action="store_true",
                     help="also run a 1 GiB copy kernel (byte-counter calibration)")
     ap.add_argument("--scale", type=int, default=20)
@@ -456,9 +643,13 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="library default launch shapes (no autotuning)")
     ap.add_argument("--sssp-only", action="store_true",
-                    help="skip the queue leg (for counter passes on the solver kernel)")
+                    help="skip every leg but the timed RMAT-20 solves (counter passes)")
+    ap.add_argument("--queue-only", action="store_true",
+                    help="only the timed queue runs (counter passes on k_bench_mixed)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-one-at-a-time legs")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="skip the grid and road legs")
     ap.add_argument("--served-requests", type=int, default=100,
                     help="requests per served run (0 skips the served leg)")
     ap.add_argument("--served-lanes", type=int, default=4,
@@ -495,15 +686,51 @@ def main():
         for row in bf_sweep(pkg, torch, dev):
             print(json.dumps(row), flush=True)
         return
+    only_timed = args.sssp_only or args.queue_only
 
     t0 = time.time()
     g = synth.rmat(args.scale)
     log(f"graph rmat{args.scale}: n={g.n} m={g.m} src={g.src} ({time.time() - t0:.1f}s)")
+    rec = golden("rmat20") if args.scale == 20 else None
+    if rec is not None:
+        assert graph_sha256(g) == rec["graph_sha256"], "rmat20: generator output changed"
     off = torch.from_numpy(g.offsets).to(dev)
     col = torch.from_numpy(g.cols).to(dev)
     w = torch.from_numpy(g.w).to(dev)
     ctx = pkg.SsspContext(g.n, g.m)
     q = pkg.Queue(QUEUE_CAP)
+    # every library object is closed explicitly, before the interpreter and
+    # the HIP runtime shut down
+    try:
+        out, parity_ok = run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q,
+                                       only_timed)
+    finally:
+        ctx.close()
+        q.close()
+    if not args.no_cpu and not only_timed:
+        log("cpu baselines ...")
+        m_reached = out["config"]["m_reached"]
+        out["cpu_baseline"] = cpu_baseline(g, m_reached)
+        out["cpu_baselines_more"] = cpu_baselines_more(g, m_reached)
+        out["cpu_queue_baselines"] = cpu_queue_baselines()
+        if not args.no_graphs:
+            # the grid and the road mesh: the full grid; road2048 with the
+            # oracle's rounds (its authority, one core); the sequential FIFO
+            # and the Jacobi rounds on the same recipe at side 512 (bounded
+            # sample: at side 2048 the FIFO form alone takes about a minute)
+            out["cpu_graph_baselines"] = cpu_graph_baselines([
+                ("grid64", synth.config_graph("grid64"), ("rounds", "fifo", "jacobi")),
+                ("road2048", synth.config_graph("road2048"), ("rounds",)),
+                ("road512_sample", synth.road(512), ("fifo", "jacobi", "rounds"))],
+                budget_s=3.0)
+        out["host"] = host_info()
+    print(json.dumps(out), flush=True)
+    if not parity_ok:
+        log("PARITY FAILURE: a timed result differs from the stored oracle result")
+        sys.exit(3)
+
+
+def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed):
     dist = torch.empty(g.n, dtype=torch.int64, device=dev)
     pred = torch.empty(g.n, dtype=torch.int32, device=dev)
 
@@ -523,7 +750,7 @@ def main():
         del a, b
 
     probes = None
-    if not args.no_probes and not args.sssp_only:
+    if not args.no_probes and not only_timed:
         probes = run_probes(pkg, torch, dev)
         log(f"probes {probes}")
 
@@ -532,7 +759,7 @@ def main():
     sssp_launch = {}
     if args.sssp_launch:
         sssp_launch = json.loads(args.sssp_launch)
-    elif not args.no_tune:
+    elif not args.no_tune and not args.queue_only:
         sssp_launch, tune_ms = ctx.autotune(off, col, w, g.src, reps=5)
         log(f"sssp autotune: {sssp_launch} {tune_ms:.3f} ms")
     queue_launch = {"ticket_batch": 1}
@@ -557,7 +784,7 @@ def main():
         queue_launch = best[1]
         log(f"queue launch: {queue_launch} {best[0]:.3f} ms (b=1 best {queue_b1_ms:.3f} ms)")
     queue_part = None
-    if not args.sssp_only:
+    if not only_timed:
         # the partitioned form (one Broker Queue per XCD, Alg. 2's layout)
         queue_part = {}
         for b in (1, 64, 256):
@@ -575,6 +802,8 @@ def main():
         st = {"ms": float("nan"), "enq_full": 0, "deq_empty": 0}
         if not args.sssp_only:
             st, _, _ = q.bench_mixed(QUEUE_OPS, launch=queue_launch)
+        if args.queue_only:
+            return st, None
         ctx.solve(off, col, w, g.src, dist=dist, pred=pred, launch=sssp_launch or None)
         return st, ctx.stats()
 
@@ -592,107 +821,152 @@ def main():
     wall = time.perf_counter() - t_start
     log(f"timed {args.steps} steps in {wall:.3f}s")
 
+    # outside the timed region: the last timed solve's output against the
+    # stored result (CPU oracle, certified by the Johnson closed form)
+    parity = None
+    if rec is not None and not args.queue_only:
+        parity = matches_golden(rec, dist, pred) and m_reached == rec["m_reached"]
+        log(f"timed output vs stored oracle result: {'exact' if parity else 'MISMATCH'}")
+
     q_ms = np.array([x["ms"] for x in qs])
-    s_ms = np.array([x["ms"] for x in ss])
-    k_ms = np.array([x["solve_ms"] for x in ss])
-    gteps = m_reached / (s_ms.mean() * 1e-3) / 1e9
-    qmops = QUEUE_OPS / (q_ms.mean() * 1e-3) / 1e6
-    deq = float(np.mean([x["dequeued"] for x in ss]))
-    rel = float(np.mean([x["relaxations"] for x in ss]))
-    push = float(np.mean([x["pushes"] for x in ss]))
-    alg_bytes = BYTES_PER_DEQ * deq + BYTES_PER_EDGE * rel + BYTES_PER_PUSH * push
-    achieved = alg_bytes / (k_ms.mean() * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": read_traffic(None), "kernel": "k_solve<64>",
-            "l2_hit_rate": read_counter_summary(L2_FILE, "k_solve", "l2_hit_rate"),
-            "algorithmic_bytes_per_launch": int(alg_bytes),
-            "kernel_ms": round(float(k_ms.mean()), 4)}
     out = {
         "metric": "SSSP GTEPS + queue Mops/s on 1 MI355X; batched/served vs one-at-a-time",
-        "value": round(gteps, 4), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "value": None, "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": f"rmat{args.scale}_sssp+queue_mixed", "n": g.n, "m": g.m,
                    "src": g.src, "m_reached": m_reached, "queue_capacity": QUEUE_CAP,
                    "queue_ops": QUEUE_OPS, "parallelism": "single_gpu"},
-        "queue_mops": round(qmops, 2),
-        "queue_mops_b1": round(QUEUE_OPS / (queue_b1_ms * 1e-3) / 1e6, 2) if queue_b1_ms else None,
-        "queue_partitioned": queue_part,
-        "launch": {"sssp": sssp_launch, "queue": queue_launch},
-        "sssp": {"ms": round(float(s_ms.mean()), 4), "ms_median": round(float(np.median(s_ms)), 4),
-                 "solver_kernel_ms": round(float(k_ms.mean()), 4),
-                 "relaxations": int(rel), "dequeued": int(deq), "pushes": int(push),
-                 "batches": int(np.mean([x["batches"] for x in ss])),
-                 "idle_polls": int(np.mean([x["idle_polls"] for x in ss])),
-                 "work_ratio_k": round(rel / m_reached, 3),
-                 "relax_per_s_G": round(rel / (k_ms.mean() * 1e-3) / 1e9, 3),
-                 "grid": int(ss[-1]["grid"])},
-        "queue": {"ms": round(float(q_ms.mean()), 4), "enq_full": int(qs[-1]["enq_full"]),
-                  "deq_empty": int(qs[-1]["deq_empty"])},
-        "roofline": roof,
+        "parity": {"rmat20_timed_output": ("exact" if parity else "MISMATCH")
+                   if parity is not None else "not checked",
+                   "reference": "tests/golden/rmat20.json (CPU oracle, Johnson-certified)"},
     }
-    # atomics the solver kernel issues (counter summary of the same sources),
-    # per second of its time, against the measured random-atomicMin rate
-    n_atomics = read_counter_summary(ATOMICS_FILE, "k_solve", "TCC_ATOMIC_sum_mean")
-    if n_atomics:
-        out["atomic_rate_G"] = round(n_atomics / (k_ms.mean() * 1e-3) / 1e9, 3)
+    if not args.sssp_only:
+        qmops = QUEUE_OPS / (q_ms.mean() * 1e-3) / 1e6
+        out["queue_mops"] = round(qmops, 2)
+        out["queue_mops_b1"] = (round(QUEUE_OPS / (queue_b1_ms * 1e-3) / 1e6, 2)
+                                if queue_b1_ms else None)
+        out["queue_partitioned"] = queue_part
+        out["queue"] = {"ms": round(float(q_ms.mean()), 4),
+                        "enq_full": int(qs[-1]["enq_full"]),
+                        "deq_empty": int(qs[-1]["deq_empty"]), "launch": queue_launch}
+        out["queue_roofline"] = queue_roofline(float(q_ms.mean()), queue_launch, queue_b1_ms,
+                                               probes)
+    if not args.queue_only:
+        s_ms = np.array([x["ms"] for x in ss])
+        k_ms = np.array([x["solve_ms"] for x in ss])
+        gteps = m_reached / (s_ms.mean() * 1e-3) / 1e9
+        out["value"] = round(gteps, 4)
+        deq = float(np.mean([x["dequeued"] for x in ss]))
+        rel = float(np.mean([x["relaxations"] for x in ss]))
+        push = float(np.mean([x["pushes"] for x in ss]))
+        alg_bytes = BYTES_PER_DEQ * deq + BYTES_PER_EDGE * rel + BYTES_PER_PUSH * push
+        achieved = alg_bytes / (k_ms.mean() * 1e-3) / 1e9
+        out["launch"] = {"sssp": sssp_launch, "queue": queue_launch}
+        out["sssp"] = {"ms": round(float(s_ms.mean()), 4),
+                       "ms_median": round(float(np.median(s_ms)), 4),
+                       "solver_kernel_ms": round(float(k_ms.mean()), 4),
+                       "relaxations": int(rel), "dequeued": int(deq), "pushes": int(push),
+                       "batches": int(np.mean([x["batches"] for x in ss])),
+                       "idle_polls": int(np.mean([x["idle_polls"] for x in ss])),
+                       "work_ratio_k": round(rel / m_reached, 3),
+                       "relax_per_s_G": round(rel / (k_ms.mean() * 1e-3) / 1e9, 3),
+                       "grid": int(ss[-1]["grid"])}
+        out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                           "traffic": read_traffic(None), "kernel": "k_solve<64>",
+                           "l2_hit_rate": read_counter_summary(L2_FILE, "k_solve",
+                                                               "l2_hit_rate"),
+                           "algorithmic_bytes_per_launch": int(alg_bytes),
+                           "kernel_ms": round(float(k_ms.mean()), 4)}
+        # atomics the solver kernel issues (counter summary of the same
+        # sources), per second of its time, against the measured
+        # random-atomicMin rate
+        n_atomics = read_counter_summary(ATOMICS_FILE, "k_solve", "TCC_ATOMIC_sum_mean")
+        if n_atomics:
+            out["atomic_rate_G"] = round(n_atomics / (k_ms.mean() * 1e-3) / 1e9, 3)
+        if probes:
+            peak = probes.get("atomic_min_rand_8MiB_Gops")
+            if peak:
+                if n_atomics:
+                    out["atomic_frac"] = round(out["atomic_rate_G"] / peak, 4)
+                # relaxations are mostly loads (the key check), not atomics
+                out["relax_rate_vs_atomic_peak"] = round(
+                    (rel / (k_ms.mean() * 1e-3) / 1e9) / peak, 4)
+            lpeak = probes.get("load_rand_8MiB_Gops")
+            if lpeak:
+                # one random coherent key load per relaxation at most
+                out["relax_rate_vs_load_peak"] = round(
+                    (rel / (k_ms.mean() * 1e-3) / 1e9) / lpeak, 4)
     if probes:
         out["probes"] = probes
-        peak = probes.get("atomic_min_rand_8MiB_Gops")
-        if peak:
-            if n_atomics:
-                out["atomic_frac"] = round(out["atomic_rate_G"] / peak, 4)
-            # relaxations are mostly loads (the key check), not atomics
-            out["relax_rate_vs_atomic_peak"] = round(
-                (rel / (k_ms.mean() * 1e-3) / 1e9) / peak, 4)
-        lpeak = probes.get("load_rand_8MiB_Gops")
-        if lpeak:
-            # one random coherent key load per relaxation at most
-            out["relax_rate_vs_load_peak"] = round(
-                (rel / (k_ms.mean() * 1e-3) / 1e9) / lpeak, 4)
-    if not args.sssp_only:
-        out["rounds_form"] = rounds_leg(pkg, torch, g, off, col, w, dist, m_reached)
-        log(f"rounds form {out['rounds_form']}")
-    if not args.no_batched and not args.sssp_only:
+    parity_ok = parity is not False
+    if only_timed:
+        return out, parity_ok
+
+    out["rounds_form"] = rounds_leg(pkg, torch, g, off, col, w, dist, m_reached)
+    log(f"rounds form {out['rounds_form']}")
+    if not args.no_graphs:
+        graphs = {}
+        # C0: the 64 x 64 grid (latency-bound: ~126 hops of queue round trips)
+        graphs["grid64"] = graph_leg(pkg, torch, dev, "grid64", synth.config_graph("grid64"),
+                                     reps=20, warmup=10, ctx=ctx)
+        log(f"grid64 {graphs['grid64']}")
+        # C2 run A: the 2048 x 2048 road mesh; run B: the planted -3 cycle
+        road = synth.config_graph("road2048")
+        graphs["road2048"] = graph_leg(pkg, torch, dev, "road2048", road, reps=5, warmup=2)
+        log(f"road2048 {graphs['road2048']}")
+        del road
+        graphs["road2048_negcycle"] = negcycle_leg(pkg, torch, dev,
+                                                   synth.config_graph("road2048_negcycle"))
+        log(f"road2048_negcycle {graphs['road2048_negcycle']}")
+        out["graphs"] = graphs
+        parity_ok &= all(v["parity"] == "exact" for v in graphs.values())
+    if not args.no_batched:
         batched = {}
-        srcs = synth.random_sources(g, 64, seed=synth.SEED_BASE + 3)
-        qs = [(off, col, w, int(sv), torch.empty(g.n, dtype=torch.int64, device=dev),
-               torch.empty(g.n, dtype=torch.int32, device=dev)) for sv in srcs]
-        blaunch = json.loads(args.batched_launch) if args.batched_launch else None
         if args.batched_only in (None, "rmat20x64"):
-            batched["rmat20_x64_sources"] = batched_leg(pkg, torch, dev, "rmat20x64", qs,
-                                                        [g] * len(qs), 5, sssp_launch or None,
-                                                        blaunch)
+            srcs = synth.random_sources(g, 64, seed=synth.SEED_BASE + 3)
+            bqs = [(off, col, w, int(sv), torch.empty(g.n, dtype=torch.int64, device=dev),
+                    torch.empty(g.n, dtype=torch.int32, device=dev)) for sv in srcs]
+            blaunch = json.loads(args.batched_launch) if args.batched_launch else None
+
+            def check_x64(queries):
+                # all 64 batched answers against the stored per-source results
+                gx = golden("rmat20_x64_sources")["queries"]
+                ok = all(src == r["src"] and matches_golden(r, d_, p_)
+                         for (_, _, _, src, d_, p_), r in zip(queries, gx))
+                return "exact (all 64 queries)" if ok else "MISMATCH"
+
+            batched["rmat20_x64_sources"] = batched_leg(
+                pkg, torch, dev, "rmat20x64", bqs, [g] * len(bqs), 5, sssp_launch or None,
+                blaunch, check=check_x64 if args.scale == 20 else None)
+            parity_ok &= batched["rmat20_x64_sources"].get("parity", "exact").startswith("exact")
             log(f"batched rmat20x64 {batched['rmat20_x64_sources']}")
-        del qs
-    if not args.no_batched and not args.sssp_only and args.batched_only in (None, "er256"):
-        t0 = time.time()
-        ers = synth.er_batch(256)
-        log(f"er256 generated in {time.time() - t0:.1f}s")
-        qs = []
-        for eg in ers:
-            qs.append((torch.from_numpy(eg.offsets).to(dev), torch.from_numpy(eg.cols).to(dev),
-                       torch.from_numpy(eg.w).to(dev), eg.src,
-                       torch.empty(eg.n, dtype=torch.int64, device=dev),
-                       torch.empty(eg.n, dtype=torch.int32, device=dev)))
-        batched["er256"] = batched_leg(pkg, torch, dev, "er256", qs, ers, 5, None, blaunch)
-        log(f"batched er256 {batched['er256']}")
-        del qs, ers
-    if not args.no_batched and not args.sssp_only:
+            del bqs
+        if args.batched_only in (None, "er256"):
+            t0 = time.time()
+            ers = synth.er_batch(256)
+            log(f"er256 generated in {time.time() - t0:.1f}s")
+            bqs = []
+            for eg in ers:
+                bqs.append((torch.from_numpy(eg.offsets).to(dev),
+                            torch.from_numpy(eg.cols).to(dev),
+                            torch.from_numpy(eg.w).to(dev), eg.src,
+                            torch.empty(eg.n, dtype=torch.int64, device=dev),
+                            torch.empty(eg.n, dtype=torch.int32, device=dev)))
+            blaunch = json.loads(args.batched_launch) if args.batched_launch else None
+            batched["er256"] = batched_leg(pkg, torch, dev, "er256", bqs, ers, 5, None, blaunch)
+            log(f"batched er256 {batched['er256']}")
+            del bqs, ers
         out["batched"] = batched
-    if args.served_requests > 0 and not args.sssp_only:
+    if args.served_requests > 0:
         t0 = time.time()
         out["served"] = served_leg(pkg, torch, dev, g, (off, col, w), args.served_requests,
                                    lanes=args.served_lanes)
         log(f"served leg in {time.time() - t0:.1f}s: {out['served']}")
-    if not args.no_cpu:
-        log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(g, m_reached)
-        out["cpu_baselines_more"] = cpu_baselines_more(g, m_reached)
-        out["cpu_queue_baselines"] = cpu_queue_baselines()
-    print(json.dumps(out), flush=True)
+    out["parity"]["all_checked_legs"] = "exact" if parity_ok else "MISMATCH"
+    return out, parity_ok
 
 
 if __name__ == "__main__":

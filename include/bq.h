@@ -45,7 +45,10 @@ typedef enum {
     BQ_EHIP = -3,     /* a HIP runtime call failed */
     BQ_ERANGE = -4,   /* distances cannot be packed: n * max|w| too large */
     BQ_ETIMEOUT = -5, /* a device-side watchdog fired; state was reset */
-    BQ_EBUSY = -6     /* object too small for this input (max_n / max_m) */
+    BQ_EBUSY = -6,    /* object too small for this input (max_n / max_m) */
+    BQ_EOVERFLOW = -7 /* a solver queue was found over capacity: the queues are
+                         sized so that this cannot happen, so it reports a
+                         library fault; the state is rebuilt on the next call */
 } bq_status;
 
 /* Opaque handles. */

@@ -15,6 +15,11 @@ a log of positions can show:
 - per-producer FIFO: items of one producer leave in the order that producer
   put them in;
 - quiescent count: at rest 0 <= tail - head <= capacity and count equals it.
+
+Pinned by tests/test_history_pins.py: histories of a sequential bounded
+FIFO pass every check; one planted defect each (a swapped position, a lost
+item, a duplicated item, a per-producer reorder, disagreeing counters) is
+rejected; and planted mistakes in these checks are caught by those pins.
 """
 from __future__ import annotations
 

@@ -15,11 +15,13 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbqsssp.so")
 
 BQ_OK, BQ_EINVAL, BQ_ENOMEM, BQ_EHIP, BQ_ERANGE, BQ_ETIMEOUT, BQ_EBUSY = 0, -1, -2, -3, -4, -5, -6
+BQ_EOVERFLOW = -7
 BQ_F_VALIDATE = 1
 BQ_F_TRACE = 2
 BQ_F_GRAPH = 4
@@ -188,6 +190,15 @@ def _check(status: int, what: str):
         raise BQError(status, what)
 
 
+def _release(self):
+    """__del__ of the handle classes: close, except while the interpreter
+    shuts down. Then the process is ending, the device frees everything, and
+    HIP calls from module teardown could run after the runtime (or a
+    profiler attached to it) has finished. Call close() to free earlier."""
+    if not sys.is_finalizing():
+        self.close()
+
+
 def _stream(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -235,7 +246,7 @@ class Queue:
             lib().bq_destroy(self.handle)
             self.handle = None
 
-    __del__ = close
+    __del__ = _release
 
     def reset(self, stream=None):
         _check(lib().bq_reset(self.handle, _stream(stream)), "bq_reset")
@@ -328,7 +339,7 @@ class SsspContext:
             lib().sssp_ctx_destroy(self.handle)
             self.handle = None
 
-    __del__ = close
+    __del__ = _release
 
     def solve(self, offsets, cols, w, src: int, dist=None, pred=None, want_pred=True,
               launch=None, validate=False, trace=False, neg_inf=False, stream=None):
@@ -401,7 +412,7 @@ class SsspBatch:
             lib().sssp_batch_destroy(self.handle)
             self.handle = None
 
-    __del__ = close
+    __del__ = _release
 
     @staticmethod
     def _table(queries):
@@ -469,7 +480,7 @@ class Server:
             lib().bq_server_destroy(self.handle)
             self.handle = None
 
-    __del__ = close
+    __del__ = _release
 
     def add_graph(self, offsets, cols, w) -> int:
         import torch
@@ -539,7 +550,7 @@ class Arena:
             lib().bq_arena_destroy(self.handle)
             self.handle = None
 
-    __del__ = close
+    __del__ = _release
 
     def alloc(self, nbytes: int):
         off = ctypes.c_uint64()
@@ -591,7 +602,7 @@ class RoundsContext:
             lib().sssp_rounds_destroy(self.handle)
             self.handle = None
 
-    __del__ = close
+    __del__ = _release
 
     def solve(self, offsets, cols, w, src: int, dist=None, pred=None, want_pred=True,
               launch=None, validate=False, neg_inf=False, stream=None):

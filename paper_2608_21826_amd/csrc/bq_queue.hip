@@ -267,6 +267,7 @@ const char* bq_strerror(bq_status s) {
         case BQ_EHIP: return "HIP runtime error";
         case BQ_ERANGE: return "distances do not fit the packed key (n * max|w| too large)";
         case BQ_ETIMEOUT: return "device watchdog fired";
+        case BQ_EOVERFLOW: return "solver queue over capacity (library fault)";
         case BQ_EBUSY: return "object too small for this input";
     }
     return "unknown status";

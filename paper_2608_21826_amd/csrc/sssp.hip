@@ -457,6 +457,7 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     const bool neg = h->negcycle.v != 0ull;
     if (err != 0ull || h->abort.v != 0ull) c->dirty = true;  // queue not quiescent
     if (err == bq::ERR_RANGE) return BQ_ERANGE;
+    if (err == bq::ERR_FULL) return BQ_EOVERFLOW;
     if (err != 0ull) return BQ_ETIMEOUT;
     *h_neg_cycle = neg ? 1 : 0;
     return BQ_OK;

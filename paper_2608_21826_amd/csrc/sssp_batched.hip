@@ -707,6 +707,7 @@ bq_status sssp_batch_finish(sssp_batch* b, int32_t* h_neg_cycle, int64_t* h_reac
         const long long err = (r >> 8) & 0xff;
         if (r & ~1ll) b->dirty = true;  // a stopped query leaves its queue non-quiescent
         if (err == bq::ERR_RANGE && ret == BQ_OK) ret = BQ_ERANGE;
+        else if (err == bq::ERR_FULL && ret == BQ_OK) ret = BQ_EOVERFLOW;
         else if (err != 0 && ret == BQ_OK) ret = BQ_ETIMEOUT;
     }
     return ret;

@@ -622,6 +622,7 @@ bq_status sssp_bf_rounds(sssp_rounds_ctx* c, int32_t n, int64_t m, const int64_t
     c->last.grid = grid;
     c->last.wg_size = L.wg_size;
     if (err == bq::ERR_RANGE) return BQ_ERANGE;
+    if (err == bq::ERR_FULL) return BQ_EOVERFLOW;
     if (err != 0ull || timed_out) return BQ_ETIMEOUT;
     *h_neg_cycle = neg ? 1 : 0;
     return BQ_OK;

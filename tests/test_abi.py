@@ -81,3 +81,16 @@ def test_struct_layouts_match_the_header(tmp_path):
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
                                           text=True).stdout.split()]
     assert got == want
+
+
+def test_status_codes_match_the_header():
+    """bq_status values in the header equal the binding's constants."""
+    import paper_2608_21826_amd as pkg
+    text = open(HEADER).read()
+    body = text[text.index("typedef enum {"):text.index("} bq_status;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    vals = {k: int(v) for k, v in re.findall(r"(BQ_\w+)\s*=\s*(-?\d+)", body)}
+    assert vals and all(getattr(pkg, k) == v for k, v in vals.items())
+    assert len(set(vals.values())) == len(vals)
+    for k in vals:
+        assert pkg.strerror(vals[k]) != "unknown status", k

@@ -4,6 +4,7 @@ sssp_bf gives it alone), whatever else shares the launch."""
 import numpy as np
 import pytest
 
+import goldens
 import oracle
 import synth
 
@@ -207,19 +208,79 @@ def test_er256_full():
     b.close()
 
 
-def test_rmat20_64_sources():
+def check_rmat20_x64(qs, neg):
+    """All 64 queries against the stored per-source results (oracle,
+    certified by the Johnson closed form)."""
+    rec = goldens.load("rmat20_x64_sources")
+    assert len(rec["queries"]) == len(qs) == len(neg)
+    torch.cuda.synchronize()
+    for (off, col, w, src, dist, pred), r, flag in zip(qs, rec["queries"], neg):
+        assert src == r["src"] and not flag
+        goldens.check(r, dist.cpu().numpy(), pred.cpu().numpy(), f"rmat20 src={src}")
+
+
+@pytest.fixture(scope="module")
+def rmat20_x64():
     g = synth.rmat(20)
+    rec = goldens.load("rmat20_x64_sources")
+    assert goldens.graph_digest(g) == rec["graph_sha256"], "generator output changed"
     t = upload(g)
-    srcs = synth.random_sources(g, 64, seed=synth.SEED_BASE + 3)
+    srcs = synth.random_sources(g, 64, seed=rec["sources_seed"])
     b = pkg.SsspBatch(64, 64 * g.n, 64 * g.m)
     qs, keep = make_queries([(g, int(s), t) for s in srcs])
+    yield g, b, qs
+    b.close()
+
+
+def test_rmat20_64_sources(rmat20_x64):
+    g, b, qs = rmat20_x64
     neg = b.solve(qs, graph=True)
     print(f"[batched] rmat20x64 stats {b.stats()}", flush=True)
-    assert not any(neg)
-    # the oracle on a sample of 12 sources (each ~0.5 s on one core)
-    sample = list(range(0, 64, 6))[:12]
-    check_all([qs[i] for i in sample], [keep[i] for i in sample], [neg[i] for i in sample])
-    b.close()
+    check_rmat20_x64(qs, neg)
+    # the oracle itself on two of them
+    sample = [0, 37]
+    check_all([qs[i] for i in sample], [(g, qs[i][3]) for i in sample], [neg[i] for i in sample])
+
+
+@pytest.mark.parametrize("launch", [{"wg_count": 256, "ticket_batch": 1},
+                                    {"wg_count": 512, "ticket_batch": 2, "row_chunk": 256},
+                                    {"wg_count": 1024, "ticket_batch": 1, "queue_scale": 1}],
+                         ids=str)
+def test_rmat20_64_sources_shapes(rmat20_x64, launch):
+    """The batched launch shapes the autotuner picks from, all 64 answers
+    exact in each; the hipGraph is replayed twice."""
+    g, b, qs = rmat20_x64
+    for _ in range(2):
+        for q in qs:
+            q[4].fill_(-7)
+        neg = b.solve(qs, launch=launch, graph=True)
+        check_rmat20_x64(qs, neg)
+
+
+def test_rmat20_64_sources_autotuned(rmat20_x64):
+    g, b, qs = rmat20_x64
+    launch, ms = b.autotune(qs)
+    print(f"[batched] rmat20x64 autotuned {launch} {ms:.3f} ms", flush=True)
+    check_rmat20_x64(qs, b.solve(qs, launch=launch, graph=True))
+
+
+def test_batched_watchdog_then_recovery(batch):
+    """timeout_us = 1 on a batch of road meshes: every query runs past its
+    deadline, the kernels leave through their own bounded checks and the
+    call returns BQ_ETIMEOUT; the next call on the same workspace is exact."""
+    items = []
+    for i in range(6):
+        g = synth.road(96 + 16 * i, plant_cycle=False, seed=8980 + i)
+        items.append((g, 0, upload(g)))
+    qs, keep = make_queries(items)
+    with pytest.raises(pkg.BQError) as ei:
+        batch.solve(qs, launch={"timeout_us": 1})
+    assert ei.value.status == pkg.BQ_ETIMEOUT
+    check_all(qs, keep, batch.solve(qs))
+    with pytest.raises(pkg.BQError) as ei:
+        batch.solve(qs, launch={"timeout_us": 1}, graph=True)
+    assert ei.value.status == pkg.BQ_ETIMEOUT
+    check_all(qs, keep, batch.solve(qs, graph=True))
 
 
 @pytest.mark.parametrize("wgs", [8, 24, 64])

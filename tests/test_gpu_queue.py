@@ -204,34 +204,78 @@ def test_partitioned_rejects_bad_segment_counts():
 @pytest.mark.parametrize("segments", [1, 8])
 @pytest.mark.parametrize("bwd", [False, True])
 def test_enqdeq_partitioned(segments, bwd):
+    """Every segment holds exactly its share of the enqueues, so no enqueue
+    can be refused under either policy (the broker reservation of a phase
+    that only enqueues never finds the count short), and the dequeue phase
+    takes every item back."""
     q = pkg.Queue(1 << 16)
     L = {"ticket_batch": 4, "segments": segments, "flags": pkg.BQ_F_BWD if bwd else 0}
     e, d = q.bench_enqdeq(1 << 17, launch=L)
-    if bwd:  # single-shot checks may refuse under contention
-        assert e["enq_ok"] <= 1 << 16 and d["deq_ok"] <= e["enq_ok"]
-    else:
-        assert e["enq_ok"] == 1 << 16 and d["deq_ok"] == 1 << 16
-        assert e["enq_full"] == 0 and d["deq_empty"] == 0
+    assert e["enq_ok"] == 1 << 16 and e["enq_full"] == 0
+    assert d["deq_ok"] == 1 << 16 and d["deq_empty"] == 0
     q.close()
 
 
-@pytest.mark.parametrize("cap,n_ops", [(1 << 16, 1 << 16), (1 << 12, 1 << 16)])
+@pytest.mark.parametrize("cap,n_ops", [(1 << 16, 1 << 16), (1 << 16, 1 << 17), (1 << 12, 1 << 16)])
 @pytest.mark.parametrize("bwd", [False, True])
 def test_enqdeq(cap, n_ops, bwd):
-    """Section IV EnqDeq: all enqueues, then all dequeues, one attempt each."""
+    """Section IV EnqDeq: all enqueues, then all dequeues, one attempt each.
+    Where the queue holds every enqueue, the count is exact under both
+    policies; past capacity BWD may refuse a little more than the room it
+    had (it never looks at the count twice), the Broker Queue exactly the
+    excess. Either way the dequeues take back what went in and the
+    counters agree at rest."""
     q = pkg.Queue(cap)
     L = {"ticket_batch": 4, "flags": pkg.BQ_F_BWD if bwd else 0}
     e, d = q.bench_enqdeq(n_ops, launch=L)
     half = n_ops // 2
-    if bwd:
-        assert e["enq_ok"] <= min(half, cap)
-    else:
+    if half <= cap or not bwd:
         assert e["enq_ok"] == min(half, cap)
-        assert e["enq_full"] >= (1 if half > cap else 0)
+        assert (e["enq_full"] > 0) == (half > cap)
+    else:
+        assert 0 < e["enq_ok"] <= cap
     assert d["deq_ok"] == e["enq_ok"]
+    h, t, c = q.counters()
+    assert c == 0 and t == h == e["enq_ok"]
+    q.close()
+
+
+@pytest.mark.parametrize("b", [1, 4])
+def test_bwd_bulk_exact_where_refusal_is_impossible(b):
+    """BWD through bq_enqueue / bq_dequeue with many waves: the enqueue fits,
+    so all of it succeeds; every value comes out exactly once (the dequeue
+    output is the log), and the queue is empty at rest."""
+    cap = 1 << 15
+    L = {"flags": pkg.BQ_F_BWD, "ticket_batch": b}
+    q = pkg.Queue(cap)
+    vals = np.random.default_rng(b).permutation(cap).astype(np.int32)
+    assert q.enqueue(torch.from_numpy(vals).cuda(), launch=L) == cap
+    out = q.dequeue(cap, launch=L).cpu().numpy()
+    assert out.size == cap
+    history.check_conservation(vals, out, np.zeros(0))
+    h, t, c = q.counters()
+    assert c == 0 and t == h == cap
+    q.close()
+
+
+def test_queue_watchdog_then_recovery():
+    """A 1 us watchdog on a tiny, crowded queue: waits for room or items
+    outlast it, so the run stops through the kernel's own bounded checks and
+    returns BQ_ETIMEOUT (the queue is reset by the call). If this box ever
+    finishes the run inside the limit, the run must be whole. Either way
+    the same queue then passes the full history checks."""
+    cap = 64
+    q = pkg.Queue(cap)
+    try:
+        st = q.bench_mixed(1 << 22, launch={"ticket_batch": 1, "timeout_us": 1})[0]
+        print(f"[queue] watchdog did not fire: {st}", flush=True)
+        assert st["enq_ok"] == st["deq_ok"] == 1 << 21
+    except pkg.BQError as ex:
+        assert ex.status == pkg.BQ_ETIMEOUT
     h, t, c = q.counters()
     assert c == 0 and t == h
     q.close()
+    _mixed(cap, 1 << 18)
 
 
 @pytest.mark.parametrize("b", [2, 8])

@@ -220,3 +220,60 @@ def test_lane_is_reported(graphs):
     assert all(0 <= x["lane"] < 3 for x in resp[:-1])
     assert resp[-1]["status"] == pkg.BQ_EINVAL and resp[-1]["lane"] == -1
     srv.close()
+
+
+def test_full_size_mix_matches_goldens():
+    """The benchmark's resident graphs at full size (RMAT-20, road2048 and
+    an ER graph of 200k vertices) with Poisson arrivals and one-off ER
+    uploads mixed in: RMAT-20 queries at the stored sources (its default
+    source and eight of the 64 batched sources) and road2048 queries at its
+    source must equal the stored results byte for byte in the mix, and the
+    others the oracle."""
+    import goldens
+    rmat, road, er = (synth.config_graph(x) for x in ("rmat20", "road2048", "er200k"))
+    r_rec, x_rec, d_rec = (goldens.load(x) for x in ("rmat20", "rmat20_x64_sources", "road2048"))
+    assert goldens.graph_digest(rmat) == r_rec["graph_sha256"]
+    assert goldens.graph_digest(road) == d_rec["graph_sha256"]
+    uploads = [synth.erdos_renyi(nv, 8, seed=synth.SEED_BASE + 60 + i)
+               for i, nv in enumerate((10_000, 60_000, 250_000))]
+    resident = [rmat, road, er]
+    srv = pkg.Server(4, 32, 8 * road.n, 8 * road.m, 2 << 30)
+    for g in resident:
+        srv.add_graph(*dev_csr(g))
+    plan = ([("g", 0, r_rec)] + [("g", 0, q) for q in x_rec["queries"][:8]] +
+            [("g", 1, d_rec), ("g", 1, d_rec)] +
+            [("g", 2, int(s)) for s in synth.random_sources(er, 4, seed=77)] +
+            [("u", i, int(i * 7919 % uploads[i].n)) for i in range(3)])
+    rng = np.random.default_rng(21)
+    order = rng.permutation(len(plan))
+    t = 0.0
+    reqs, truth = [], []
+    for k in order:
+        kind, gi, what = plan[k]
+        g = resident[gi] if kind == "g" else uploads[gi]
+        src = what["src"] if isinstance(what, dict) else what
+        t += rng.exponential(3000.0)
+        r = {"arrival_us": t, "src": src,
+             "dist": torch.empty(g.n, dtype=torch.int64, device=DEV),
+             "pred": torch.empty(g.n, dtype=torch.int32, device=DEV)}
+        if kind == "g":
+            r["graph"] = gi
+        else:
+            r["upload"] = host_csr(g)
+        reqs.append(r)
+        truth.append((g, src, what))
+    print(f"[served] full-size mix of {len(reqs)} requests", flush=True)
+    resp, st = srv.run(reqs)
+    print(f"[served] full-size mix {st}", flush=True)
+    torch.cuda.synchronize()
+    for r, (g, src, what), x in zip(reqs, truth, resp):
+        assert x["status"] == 0 and not x["neg_cycle"]
+        d, p = r["dist"].cpu().numpy(), r["pred"].cpu().numpy()
+        if isinstance(what, dict):
+            goldens.check(what, d, p, f"{g.name} src={src} in the mix")
+            assert x["reached_edges"] == what["m_reached"]
+        else:
+            d_ref, p_ref, _ = oracle.sssp(g, src, method="fifo")
+            assert np.array_equal(d, d_ref) and np.array_equal(p, p_ref)
+    assert st["max_lanes_busy"] >= 2
+    srv.close()

@@ -9,6 +9,7 @@ import os
 import numpy as np
 import pytest
 
+import goldens
 import oracle
 import synth
 
@@ -312,30 +313,64 @@ def test_rmat20_full(big_ctx):
     print("[sssp] rmat20 stats", big_ctx.stats(), flush=True)
 
 
-def _golden():
-    return json.load(open(os.path.join(HERE, "golden", "road2048.json")))
+# Launch shapes of the autotuner's family (workgroup count, queue segments,
+# row chunk, ticket batch, broker policy); the bench runs one of them.
+RMAT_SHAPES = [
+    None,
+    {"wg_count": 192, "segments": 2},
+    {"wg_count": 256, "segments": 4},
+    {"wg_count": 128, "segments": 2, "row_chunk": 64},
+    {"wg_count": 216, "segments": 2, "row_chunk": 256},
+    {"wg_count": 384, "segments": 8, "ticket_batch": 2},
+    {"wg_count": 96, "segments": 1, "ticket_batch": 4},
+    {"wg_count": 192, "segments": 2, "flags": pkg.BQ_F_BWD},
+]
 
 
-def _digest(a):
-    import hashlib
-    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+@pytest.fixture(scope="module")
+def rmat20():
+    g = synth.config_graph("rmat20")
+    rec = goldens.load("rmat20")
+    assert goldens.graph_digest(g) == rec["graph_sha256"], "generator output changed"
+    return g, _dev(g), rec
+
+
+@pytest.mark.parametrize("launch", RMAT_SHAPES, ids=lambda x: json.dumps(x))
+def test_rmat20_golden_shapes(big_ctx, rmat20, launch):
+    """RMAT-20 at full size in every shape the autotuner may pick: the
+    stored result (oracle, certified by the Johnson closed form), byte for
+    byte."""
+    g, (off, col, w), rec = rmat20
+    print(f"[sssp] rmat20 golden launch={launch}", flush=True)
+    dist, pred, neg = big_ctx.solve(off, col, w, g.src, launch=launch)
+    assert not neg
+    goldens.check(rec, dist.cpu().numpy(), pred.cpu().numpy(), f"rmat20 {launch}")
+
+
+def test_rmat20_autotuned_shape(big_ctx, rmat20):
+    """The shape the autotuner picks on this machine, as the benchmark times it."""
+    g, (off, col, w), rec = rmat20
+    launch, ms = big_ctx.autotune(off, col, w, g.src, reps=3)
+    print(f"[sssp] rmat20 autotuned {launch} {ms:.3f} ms", flush=True)
+    for _ in range(3):
+        dist, pred, neg = big_ctx.solve(off, col, w, g.src, launch=launch)
+        assert not neg
+        goldens.check(rec, dist.cpu().numpy(), pred.cpu().numpy(), f"rmat20 {launch}")
 
 
 def test_road2048_full(big_ctx):
-    rec = _golden()["road2048"]
+    rec = goldens.load("road2048")
     g = synth.config_graph("road2048")
+    assert goldens.graph_digest(g) == rec["graph_sha256"], "generator output changed"
     d, p, neg = run(big_ctx, g, validate=False)
     print("[sssp] road2048 stats", big_ctx.stats(), flush=True)
     assert not neg
-    idx = np.array(rec["sample_idx"])
-    assert np.array_equal(d[idx], np.array(rec["sample_dist"]))
-    assert np.array_equal(p[idx], np.array(rec["sample_pred"]))
-    assert _digest(d) == rec["dist_sha256"]
-    assert _digest(p) == rec["pred_sha256"]
+    goldens.check(rec, d, p, "road2048")
 
 
 def test_road2048_planted_negative_cycle(big_ctx):
     g = synth.config_graph("road2048_negcycle")
+    assert goldens.load("road2048_negcycle")["neg_cycle"]
     d, p, neg = run(big_ctx, g, validate=False)
     print("[sssp] road2048_negcycle stats", big_ctx.stats(), flush=True)
     assert neg
@@ -351,3 +386,28 @@ def test_road2048_negative_cycle_marks_everything(big_ctx):
     print("[sssp] road2048_negcycle marking stats", big_ctx.stats(), flush=True)
     assert neg
     assert bool((dist == np.iinfo(np.int64).min).all()) and bool((pred == -1).all())
+
+
+# ---------------------------------------------------------------------------
+# watchdog: a wait limit far below the solve time
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("launch", [{}, {"segments": 1, "ticket_batch": 4},
+                                    {"flags": pkg.BQ_F_BWD, "wg_count": 64}])
+def test_watchdog_fires_then_context_recovers(ctx, launch):
+    """timeout_us = 1: the solve (milliseconds on this 256 x 256 mesh) runs
+    past its deadline of ten wait limits, so every wave leaves through the
+    kernel's own bounded checks and the call returns BQ_ETIMEOUT. The context
+    rebuilds its queue on the next call, which must be exact."""
+    g = synth.road(256, plant_cycle=False, seed=8970)
+    off, col, w = _dev(g)
+    print(f"[sssp] watchdog launch={launch}", flush=True)
+    with pytest.raises(pkg.BQError) as ei:
+        ctx.solve(off, col, w, g.src, launch=dict(launch, timeout_us=1))
+    assert ei.value.status == pkg.BQ_ETIMEOUT
+    check(ctx, g, launch=launch or None, method="fifo")
+    # a second expiry right after a clean solve, then a clean solve again
+    with pytest.raises(pkg.BQError) as ei:
+        ctx.solve(off, col, w, g.src, launch={"timeout_us": 1})
+    assert ei.value.status == pkg.BQ_ETIMEOUT
+    check(ctx, g, method="fifo")
