@@ -266,6 +266,26 @@ bq_status sssp_bf(sssp_ctx* ctx, int32_t n, int64_t m, const int64_t* d_offsets,
                   int32_t* d_pred, int32_t* h_neg_cycle, const bq_launch* launch,
                   void* stream);
 
+/* sssp_bf without a context, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, outputs, conventions and errors as
+ * sssp_bf minus the context; it calls no allocating routine. Its workspace
+ * (queue slots, control blocks, chunk table) lives in a device array of
+ * 128 MiB that the library's code object reserves on every device it runs
+ * on, for the life of the process; each call clears the part it uses.
+ * Limit: with S queue segments (launch->segments, default min(8,
+ * workgroups)), 2 S P slots of 8 bytes, P = the power of two >= 2 (n +
+ * m/64 + 1) and >= 4096, plus about 100 KiB + 4 m / C bytes (C = row
+ * chunk) must fit 128 MiB: n + m/64 + 1 <= 2^18 with 8 segments, <= 2^21
+ * with one (an ER graph of 200k vertices and 1.6M edges fits with 8).
+ * Larger inputs return BQ_EBUSY. BQ_F_TRACE
+ * is rejected (BQ_EINVAL). All calls on one device share the array: calls
+ * that overlap in time on one device race and give undefined results.
+ * Synchronous. */
+bq_status sssp_bf_noalloc(int32_t n, int64_t m, const int64_t* d_offsets, const int32_t* d_cols,
+                          const int32_t* d_w, int32_t src, int64_t* d_dist, int32_t* d_pred,
+                          int32_t* h_neg_cycle, const bq_launch* launch, void* stream);
+
 /* Autotuner: time sssp_bf on this input (d_dist is used as scratch) for
  * workgroup counts 4, 8, 16, ... up to the co-resident maximum (stopping
  * once clearly past the fastest) and 3/4 and 3/2 of the fastest, then

@@ -39,6 +39,7 @@ EXPORTS = [
     "bq_arena_alloc", "bq_arena_free", "bq_arena_usage",
     "bq_strerror", "bq_device_cus", "bq_probe",
     "sssp_rounds_create", "sssp_rounds_destroy", "sssp_bf_rounds", "sssp_rounds_last_stats",
+    "sssp_bf_noalloc",
 ]
 
 
@@ -140,6 +141,7 @@ def lib(path: str | None = None):
         "sssp_ctx_destroy": ([vp], i32),
         "sssp_bf": ([vp, i32, i64, vp, vp, vp, i32, vp, vp, P(i32), P(Launch), vp], i32),
         "sssp_last_stats": ([vp, P(SsspStats)], i32),
+        "sssp_bf_noalloc": ([i32, i64, vp, vp, vp, i32, vp, vp, P(i32), P(Launch), vp], i32),
         "sssp_last_trace": ([vp, P(u64), i32], i32),
         "sssp_autotune": ([vp, i32, i64, vp, vp, vp, i32, vp, P(Launch), i32, P(Launch),
                            P(ctypes.c_double), vp], i32),
@@ -382,6 +384,21 @@ class SsspContext:
         s = SsspStats()
         _check(lib().sssp_last_stats(self.handle, ctypes.byref(s)), "sssp_last_stats")
         return s.as_dict()
+
+
+def sssp_bf_noalloc(offsets, cols, w, src: int, dist, pred=None, launch=None,
+                    validate=False, neg_inf=False, stream=None):
+    """sssp_bf_noalloc on device tensors: the solver with its workspace in
+    the library's fixed device array (no allocation by the library; the
+    caller passes dist and optionally pred). Returns neg (bool)."""
+    n, m, dist, pred, L = _solve_args(offsets, cols, w, dist, pred, False, launch,
+                                      (BQ_F_VALIDATE if validate else 0) |
+                                      (BQ_F_NEGINF if neg_inf else 0))
+    neg = ctypes.c_int32(0)
+    _check(lib().sssp_bf_noalloc(n, m, _ptr(offsets), _ptr(cols), _ptr(w), int(src), _ptr(dist),
+                                 _ptr(pred), ctypes.byref(neg), _launch(L), _stream(stream)),
+           "sssp_bf_noalloc")
+    return bool(neg.value)
 
 
 def sssp_bf(offsets, cols, w, src: int, want_pred=True, launch=None, validate=True, ctx=None):

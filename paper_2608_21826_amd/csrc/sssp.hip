@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "csr_device.hpp"
@@ -464,3 +465,219 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// sssp_bf_noalloc: sssp_bf for callers that cannot allocate device memory
+// ---------------------------------------------------------------------------
+// The workspace of one call (control blocks, weight-range partials, chunk
+// table, queue slots) lives in the file-scope device array `scratch`: the
+// code object reserves it on every device the library runs on, for the
+// life of the process. Host code must not pass the array's name to a kernel
+// (that is a host-side stand-in, not a device address): the device address
+// comes from hipGetSymbolAddress, once per device, with that device
+// current, and is kept per device in g_scratch.
+namespace {
+
+constexpr unsigned long long NOALLOC_SCRATCH_BYTES = 128ull << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[NOALLOC_MAX_DEVICES];      // device address per device
+int g_scratch_per_cu[NOALLOC_MAX_DEVICES][3];        // occupancy of k_solve<64/128/256>
+
+inline unsigned long long round256(unsigned long long x) { return (x + 255ull) & ~255ull; }
+
+// Device address of `scratch` on the current device (looked up on the first
+// call there).
+bq_status scratch_of_current_device(int* dev_out, unsigned char** out) {
+    int dev = 0;
+    BQ_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return BQ_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        BQ_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return BQ_EHIP;
+        g_scratch[dev] = (unsigned char*)p;
+    }
+    *dev_out = dev;
+    *out = g_scratch[dev];
+    return BQ_OK;
+}
+
+bq_status noalloc_max_grid(int dev, int batch, int* out) {
+    const int slot = batch == 1 ? 0 : (batch == 2 ? 1 : 2);
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        per_cu = g_scratch_per_cu[dev][slot];
+    }
+    if (per_cu == 0) {
+        switch (batch) {
+            case 1:
+                BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<64>,
+                                                                        SOLVE_WG_ONE, 0));
+                break;
+            case 2:
+                BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<128>,
+                                                                        SOLVE_WG_ONE, 0));
+                break;
+            default:
+                BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<256>,
+                                                                        SOLVE_WG_ONE, 0));
+                break;
+        }
+        if (per_cu < 1) per_cu = 1;
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        g_scratch_per_cu[dev][slot] = per_cu;
+    }
+    *out = per_cu * bqh::device_cus();
+    return BQ_OK;
+}
+
+// zero `words` 64-bit words (a kernel rather than a memset, so that the
+// sequence stays a plain chain of kernels)
+__global__ void k_zero_words(unsigned long long* p, unsigned long long words) {
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+         i < words; i += stride)
+        p[i] = 0ull;
+}
+
+}  // namespace
+
+extern "C" bq_status sssp_bf_noalloc(int32_t n, int64_t m, const int64_t* d_offsets,
+                                     const int32_t* d_cols, const int32_t* d_w, int32_t src,
+                                     int64_t* d_dist, int32_t* d_pred, int32_t* h_neg_cycle,
+                                     const bq_launch* launch, void* stream) {
+    if (!d_offsets || !d_dist || !h_neg_cycle) return BQ_EINVAL;
+    if (n < 1 || m < 0 || src < 0 || src >= n) return BQ_EINVAL;
+    if (m > 0 && (!d_cols || !d_w)) return BQ_EINVAL;
+    unsigned clog = DEFAULT_CHUNK_LOG;
+    if (launch && launch->row_chunk > 0) {
+        const int rc = launch->row_chunk;
+        if (rc & (rc - 1)) return BQ_EINVAL;
+        clog = bqh::log2_exact((unsigned long long)rc);
+        if (clog < MIN_CHUNK_LOG || clog > MAX_CHUNK_LOG) return BQ_EINVAL;
+    }
+    if ((unsigned long long)n + ((unsigned long long)m >> clog) + 1ull >= 0xFFFFFFFFull)
+        return BQ_EINVAL;
+    bqh::Launch L = bqh::resolve(launch, 0);
+    if (L.batch != 1 && L.batch != 2 && L.batch != 4) return BQ_EINVAL;
+    if (L.flags & BQ_F_TRACE) return BQ_EINVAL;  // the timeline needs a context
+    hipStream_t s = bqh::as_stream(stream);
+    int dev = 0;
+    unsigned char* base = nullptr;
+    {
+        bq_status st = scratch_of_current_device(&dev, &base);
+        if (st != BQ_OK) return st;
+    }
+    int max_grid = 0;
+    {
+        bq_status st = noalloc_max_grid(dev, L.batch, &max_grid);
+        if (st != BQ_OK) return st;
+    }
+    int grid = L.wg_count > 0 ? L.wg_count : default_grid(n, (long long)m, max_grid);
+    if (grid > max_grid) grid = max_grid;
+    int nseg = L.segments > 0 ? L.segments : (grid < (int)MAX_SEG ? grid : (int)MAX_SEG);
+    if (nseg > (int)MAX_SEG) return BQ_EINVAL;
+
+    // layout of this call in the scratch array: control blocks of all MAX_Q
+    // queues (k_init reads every block), weight-range partials, chunk
+    // table, then the slots of the 2 * nseg queues it uses (each sized as in
+    // sssp_ctx_create: 2 * pow2(n + m / 64 + 1), at least 4096)
+    const unsigned long long need =
+        (unsigned long long)n + ((unsigned long long)m >> MIN_CHUNK_LOG) + 1ull;
+    unsigned long long cap = 4096ull;
+    while (cap < 2ull * need) cap <<= 1;
+    const unsigned long long ctrl_bytes = round256(sizeof(bq::Ctrl) * MAX_Q);
+    const unsigned long long wr_bytes = round256(sizeof(int) * 2 * INIT_MAX_BLOCKS);
+    const unsigned long long ch_bytes =
+        round256(sizeof(unsigned) * (((unsigned long long)m >> clog) + 1ull));
+    const unsigned long long slot_words = 2ull * (unsigned long long)nseg * cap;
+    const unsigned long long total = ctrl_bytes + wr_bytes + ch_bytes + 8ull * slot_words;
+    if (cap > (1ull << 31) || total > NOALLOC_SCRATCH_BYTES) return BQ_EBUSY;
+    bq::Ctrl* ctrl = (bq::Ctrl*)base;
+    int* wrange = (int*)(base + ctrl_bytes);
+    unsigned* chunk_owner = (unsigned*)(base + ctrl_bytes + wr_bytes);
+    unsigned long long* slots = (unsigned long long*)(base + ctrl_bytes + wr_bytes + ch_bytes);
+
+    // the array keeps the previous call's contents: clear the control
+    // blocks and the slots this call uses
+    hipLaunchKernelGGL(k_zero_words, dim3(64), dim3(256), 0, s, (unsigned long long*)ctrl,
+                       (unsigned long long)(ctrl_bytes / 8));
+    BQ_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_zero_words, dim3(grid_for((int)std::min<unsigned long long>(
+                                          slot_words / 8, (unsigned long long)INT_MAX))),
+                       dim3(256), 0, s, slots, slot_words);
+    BQ_HIP_TRY(hipGetLastError());
+
+    Queue q;
+    q.slots = (decltype(q.slots))slots;
+    q.ctrl = (decltype(q.ctrl))ctrl;
+    q.sig = (decltype(q.sig))ctrl;
+    q.logN = bqh::log2_exact(cap);
+    q.pad = 0;
+    q.N = cap;
+    if (L.flags & BQ_F_VALIDATE) {
+        hipLaunchKernelGGL(k_validate_csr,
+                           dim3(grid_for((int)(m > n ? (m > INT_MAX ? INT_MAX : m) : n))),
+                           dim3(256), 0, s, (const long long*)d_offsets, (const int*)d_cols, n,
+                           (long long)m, &ctrl->aux[3].v);
+        BQ_HIP_TRY(hipGetLastError());
+        unsigned long long bad = 0;
+        BQ_HIP_TRY(hipMemcpyAsync(&bad, &ctrl->aux[3].v, 8, hipMemcpyDeviceToHost, s));
+        BQ_HIP_TRY(hipStreamSynchronize(s));
+        if (bad) return BQ_EINVAL;
+    }
+    const unsigned shift = key_shift(n);
+    SolveArgs a;
+    a.q = q;
+    a.off = (decltype(a.off))d_offsets;
+    a.col = (decltype(a.col))d_cols;
+    a.w = (decltype(a.w))d_w;
+    a.key = (decltype(a.key))d_dist;
+    a.chunk_owner = (decltype(a.chunk_owner))chunk_owner;
+    a.wrange = (decltype(a.wrange))wrange;
+    a.n = n;
+    a.src = src;
+    a.m = (long long)m;
+    a.shift = shift;
+    a.chunk_log = clog;
+    a.limit = L.limit;
+    a.deadline = 10ull * L.limit;
+    a.trace = nullptr;
+    a.trace_shift = 0;
+    a.trace_cap = 0;
+    a.bwd = (L.flags & BQ_F_BWD) ? 1u : 0u;
+    a.nseg = (unsigned)nseg;
+    a.neginf = (L.flags & BQ_F_NEGINF) ? 1u : 0u;
+    {
+        const long long big = m > n ? m : n;
+        long long blocks = (big + (long long)INIT_WG * 8 - 1) / ((long long)INIT_WG * 8);
+        if (blocks < 1) blocks = 1;
+        if (blocks > INIT_MAX_BLOCKS) blocks = INIT_MAX_BLOCKS;
+        hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(INIT_WG), 0, s, q,
+                           (long long*)d_dist, n, src, shift, (const int*)d_w, (long long)m,
+                           wrange);
+        BQ_HIP_TRY(hipGetLastError());
+    }
+    {
+        bq_status st = launch_solve(a, L.batch, grid, s);
+        if (st != BQ_OK) return st;
+    }
+    hipLaunchKernelGGL(k_unpack, dim3(grid_for(n)), dim3(256), 0, s, (long long*)d_dist,
+                       (int*)d_pred, n, src, shift);
+    BQ_HIP_TRY(hipGetLastError());
+    unsigned long long words[3] = {0, 0, 0};
+    BQ_HIP_TRY(hipMemcpyAsync(&words[0], &ctrl->error.v, 8, hipMemcpyDeviceToHost, s));
+    BQ_HIP_TRY(hipMemcpyAsync(&words[1], &ctrl->negcycle.v, 8, hipMemcpyDeviceToHost, s));
+    BQ_HIP_TRY(hipMemcpyAsync(&words[2], &ctrl->abort.v, 8, hipMemcpyDeviceToHost, s));
+    BQ_HIP_TRY(hipStreamSynchronize(s));
+    if (words[0] == bq::ERR_RANGE) return BQ_ERANGE;
+    if (words[0] == bq::ERR_FULL) return BQ_EOVERFLOW;
+    if (words[0] != 0ull) return BQ_ETIMEOUT;
+    *h_neg_cycle = words[1] != 0ull ? 1 : 0;
+    return BQ_OK;
+}
