@@ -91,7 +91,7 @@ typedef struct {
 
 #define BQ_F_VALIDATE 1u  /* sssp_bf: check the CSR on the device first */
 #define BQ_F_TRACE 2u     /* sssp_bf: record a timeline (see sssp_last_trace) */
-#define BQ_F_BWD 8u       /* the Broker Work Distributor policy (Section II):
+#define BQ_F_BWD 8u       /* the Broker Work Distributor policy (Section III.A):
                              single-shot broker check. Queue operations: an
                              operation whose reservation falls short returns
                              Full / Empty at once instead of re-checking head

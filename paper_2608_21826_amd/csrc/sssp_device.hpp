@@ -231,7 +231,16 @@ __device__ bool flush_out(const SolveArgs& a, const Queue& seg, const unsigned* 
     unsigned long long base = 0;
     if (lane == 0) {
         // pending, ENSURE on count and the tail positions as three atomics in
-        // flight together. In the solver the broker reservation cannot fail:
+        // flight together. Ordering of the pending raise before the items:
+        // the slot stores below are issued only after the wave has the tail
+        // atomic's return value (bcast64 waits for it), and gfx9-class
+        // hardware (gfx950 included) retires a wave's vector memory
+        // operations, no-return atomics among them, in issue order, so by
+        // then the pending add has been performed at the device coherence
+        // point. A consumer can only retire these items (and subtract them
+        // from pending) after reading their slots, so pending never
+        // counts them out before it counted them in.
+        // In the solver the broker reservation cannot fail:
         // a vertex holds at most one queue item (its q bit) and chunk items
         // are bounded, and each segment holds twice that, so count + cnt <= N
         // always; an overflow would be a bug and stops the solve.
