@@ -105,6 +105,13 @@ typedef struct {
                              cycle that src reaches (pred[v] = -1), exact
                              distances and predecessors for the others, and
                              the negative-cycle flag is still set. */
+#define BQ_F_NOREMAP 32u  /* sssp_bf_batched: keep the keys of queries that share a
+                             graph in vertex order in their dist buffers. By
+                             default each graph that two or more queries of the
+                             batch share gets a degree-class key layout in the
+                             workspace (key positions ordered by out-degree
+                             class, highest first, then by id), rebuilt on
+                             every call; results are the same bytes either way */
 #define BQ_F_GRAPH 4u     /* sssp_bf_batched: run the launch sequence as a hipGraph,
                              captured on first use and replayed while the batch
                              keeps its count and shape */

@@ -27,6 +27,7 @@ BQ_F_TRACE = 2
 BQ_F_GRAPH = 4
 BQ_F_BWD = 8
 BQ_F_NEGINF = 16
+BQ_F_NOREMAP = 32
 
 # every symbol include/bq.h declares
 EXPORTS = [

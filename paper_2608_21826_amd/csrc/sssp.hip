@@ -398,6 +398,10 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     a.bwd = (L.flags & BQ_F_BWD) ? 1u : 0u;
     a.nseg = (unsigned)nseg;
     a.neginf = (L.flags & BQ_F_NEGINF) ? 1u : 0u;
+    a.tcol = nullptr;
+    a.tw = nullptr;
+    a.orig = nullptr;
+    a.pos = nullptr;
     if (L.flags & BQ_F_TRACE) {
         // about 256 samples per n + m/C items of work
         unsigned long long unit = (unsigned long long)n + ((unsigned long long)m >> clog);
@@ -653,6 +657,10 @@ extern "C" bq_status sssp_bf_noalloc(int32_t n, int64_t m, const int64_t* d_offs
     a.bwd = (L.flags & BQ_F_BWD) ? 1u : 0u;
     a.nseg = (unsigned)nseg;
     a.neginf = (L.flags & BQ_F_NEGINF) ? 1u : 0u;
+    a.tcol = nullptr;
+    a.tw = nullptr;
+    a.orig = nullptr;
+    a.pos = nullptr;
     {
         const long long big = m > n ? m : n;
         long long blocks = (big + (long long)INIT_WG * 8 - 1) / ((long long)INIT_WG * 8);

@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <map>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -40,6 +41,7 @@ constexpr int BINIT_WG = 256;
 
 struct InstDesc {
     SolveArgs a;
+    long long* dist;  // the caller's output (a.key itself unless the key layout is remapped)
     int* pred;
     int orig;        // index in the caller's array
     int unit_begin;  // units [unit_begin, unit_end) belong to this query
@@ -52,6 +54,163 @@ struct Unit {
     int pad;
     long long v0, v1, e0, e1;
 };
+
+// Degree-class key layout of a graph that several queries of the batch share
+// (see remap in sssp_bf_batched_start): key positions are ordered by class of
+// out-degree, highest first, then by vertex id, so that the keys of the
+// vertices most edges point at share few cache lines and stay in L2.
+constexpr int RM_CLASSES = 16;   // class = 15 - min(15, floor(log2(degree + 1)))
+constexpr int RM_TILE = 1024;    // vertices per tile of the stable partition
+
+struct RemapDesc {
+    const long long* off;
+    const int* col;
+    const int* w;
+    unsigned* tcol;  // [m] key position of each edge's target, rows ordered by class
+    int* tw;         // [m] the edge weights in that order
+    unsigned* pos;   // [n]
+    unsigned* orig;  // [n]
+    unsigned char* cls;  // [n] class of each vertex
+    int* hist;       // [tiles * RM_CLASSES]: class counts, then their bases
+    int n;
+    int tiles;
+    long long m;
+    int tile_begin;  // tiles of earlier remapped graphs
+    int pad;
+};
+
+__device__ __forceinline__ int rm_class(const long long* off, int v) {
+    const unsigned long long d = (unsigned long long)(off[v + 1] - off[v]);
+    const int lg = 63 - __clzll(d + 1ull);
+    return RM_CLASSES - 1 - (lg < RM_CLASSES - 1 ? lg : RM_CLASSES - 1);
+}
+
+// the remapped graph and tile of global tile index g
+__device__ __forceinline__ int rm_find(const RemapDesc* R, int nr, int g) {
+    int r = 0;
+    while (r + 1 < nr && R[r + 1].tile_begin <= g) ++r;
+    return r;
+}
+
+// class counts of every tile (one wave per tile)
+__global__ void k_rm_hist(const RemapDesc* R, int nr, int total_tiles) {
+    const int lane = bq::lane_id();
+    for (int g = blockIdx.x; g < total_tiles; g += gridDim.x) {
+        const RemapDesc& d = R[rm_find(R, nr, g)];
+        const int tile = g - d.tile_begin;
+        int cnt[RM_CLASSES];
+        for (int c = 0; c < RM_CLASSES; ++c) cnt[c] = 0;
+        for (int v0 = tile * RM_TILE; v0 < (tile + 1) * RM_TILE && v0 < d.n; v0 += 64) {
+            const int v = v0 + lane;
+            const int c = v < d.n ? rm_class(d.off, v) : -1;
+            for (int k = 0; k < RM_CLASSES; ++k) cnt[k] += __popcll(bq::ballot(c == k));
+        }
+        if (lane < RM_CLASSES) {
+            int x = 0;
+            for (int k = 0; k < RM_CLASSES; ++k) x = lane == k ? cnt[k] : x;
+            d.hist[tile * RM_CLASSES + lane] = x;
+        }
+    }
+}
+
+// exclusive scan of the counts in (class, tile) order: one workgroup of 1024
+// threads per remapped graph
+__global__ __launch_bounds__(1024) void k_rm_scan(const RemapDesc* R, int nr) {
+    __shared__ int part[1024 / 64];
+    for (int r = blockIdx.x; r < nr; r += gridDim.x) {
+        const RemapDesc& d = R[r];
+        int carry = 0;
+        for (int c = 0; c < RM_CLASSES; ++c) {
+            for (int t0 = 0; t0 < d.tiles; t0 += 1024) {
+                const int t = t0 + (int)threadIdx.x;
+                const int x = t < d.tiles ? d.hist[t * RM_CLASSES + c] : 0;
+                const int incl = bq::wave_incl_scan(x);
+                if (bq::lane_id() == 63) part[threadIdx.x >> 6] = incl;
+                __syncthreads();
+                int before = carry;
+                for (int k = 0; k < (int)(threadIdx.x >> 6); ++k) before += part[k];
+                int tot = 0;
+                for (int k = 0; k < 1024 / 64; ++k) tot += part[k];
+                __syncthreads();
+                if (t < d.tiles) d.hist[t * RM_CLASSES + c] = before + incl - x;
+                carry += tot;
+            }
+        }
+    }
+}
+
+// key position of every vertex: its class's base in its tile plus its rank
+// among the tile's vertices of that class (one wave per tile, so positions
+// follow vertex ids within a class)
+__global__ void k_rm_place(const RemapDesc* R, int nr, int total_tiles) {
+    const int lane = bq::lane_id();
+    for (int g = blockIdx.x; g < total_tiles; g += gridDim.x) {
+        const RemapDesc& d = R[rm_find(R, nr, g)];
+        const int tile = g - d.tile_begin;
+        int next = lane < RM_CLASSES ? d.hist[tile * RM_CLASSES + lane] : 0;
+        for (int v0 = tile * RM_TILE; v0 < (tile + 1) * RM_TILE && v0 < d.n; v0 += 64) {
+            const int v = v0 + lane;
+            const int c = v < d.n ? rm_class(d.off, v) : -1;
+            unsigned p = 0;
+            for (int k = 0; k < RM_CLASSES; ++k) {
+                const unsigned long long mk = bq::ballot(c == k);
+                const int base = __shfl(next, k, 64);
+                if (c == k) p = (unsigned)(base + bq::rank_in(mk));
+                if (lane == k) next += __popcll(mk);
+            }
+            if (v < d.n) {
+                d.pos[v] = p;
+                d.orig[p] = (unsigned)v;
+                d.cls[v] = (unsigned char)c;
+            }
+        }
+    }
+}
+
+// Every row of every remapped graph, reordered by the class of its targets
+// (stable, so each class keeps the row's order), into tcol (target key
+// positions) and tw (weights): a wave's lanes then read the keys of the
+// most pointed-at targets first and side by side. One wave per row.
+__global__ void k_rm_rows(const RemapDesc* R, int nr) {
+    const int lane = bq::lane_id();
+    const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
+    const long long wave = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    for (int r = 0; r < nr; ++r) {
+        const RemapDesc& d = R[r];
+        for (long long u = wave; u < d.n; u += waves) {
+            const long long s = d.off[u], e = d.off[u + 1];
+            int cnt[RM_CLASSES];
+            for (int k = 0; k < RM_CLASSES; ++k) cnt[k] = 0;
+            for (long long e0 = s; e0 < e; e0 += 64) {
+                const long long i = e0 + lane;
+                const int c = i < e ? (int)d.cls[d.col[i]] : -1;
+                for (int k = 0; k < RM_CLASSES; ++k) cnt[k] += __popcll(bq::ballot(c == k));
+            }
+            int base[RM_CLASSES];
+            int run = 0;
+            for (int k = 0; k < RM_CLASSES; ++k) {
+                base[k] = run;
+                run += cnt[k];
+            }
+            for (long long e0 = s; e0 < e; e0 += 64) {
+                const long long i = e0 + lane;
+                const bool live = i < e;
+                const int v = live ? d.col[i] : 0;
+                const int c = live ? (int)d.cls[v] : -1;
+                long long at = 0;
+                for (int k = 0; k < RM_CLASSES; ++k) {
+                    const unsigned long long mk = bq::ballot(c == k);
+                    if (c == k) at = s + base[k] + bq::rank_in(mk);
+                    base[k] += __popcll(mk);
+                }
+                if (live) {
+                    d.tcol[at] = d.pos[v];
+                    d.tw[at] = d.w[i];
+                }
+            }
+        }
+    }
+}
 
 // Workgroups are dispatched to the XCDs in turn (workgroup i on XCD i mod 8),
 // so workgroup i claims from list i mod n_lists.
@@ -75,8 +234,9 @@ __global__ __launch_bounds__(BINIT_WG) void k_binit(const InstDesc* D, const Uni
         const InstDesc& d = D[un.inst];
         const SolveArgs& a = d.a;
         const long long srckey = pack_key(0, (1u << (a.shift - 1u)) - 1u, a.shift);
+        const long long spos = (long long)pos_of(a, (unsigned)a.src);
         for (long long v = un.v0 + threadIdx.x; v < un.v1; v += blockDim.x)
-            a.key[v] = (v == a.src) ? srckey : KEY_INF;
+            a.key[v] = (v == spos) ? srckey : KEY_INF;
         int lo = INT_MAX, hi = INT_MIN;
         for (long long e = un.e0 + threadIdx.x; e < un.e1; e += blockDim.x) {
             const int x = a.w[e];
@@ -116,7 +276,7 @@ __global__ __launch_bounds__(BINIT_WG) void k_binit(const InstDesc* D, const Uni
                 const unsigned long long pos = c->tail.v;
                 const unsigned slot = (unsigned)(pos & (a.q.N - 1ull));
                 const unsigned round = (unsigned)(pos >> a.q.logN);
-                a.q.slots[slot] = bq::slot_word(2u * round + 1u, (unsigned)a.src);
+                a.q.slots[slot] = bq::slot_word(2u * round + 1u, (unsigned)spos);
                 c->tail.v = pos + 1ull;
                 c->count.v = 1ull;
             }
@@ -207,16 +367,16 @@ __global__ void k_bunpack(const InstDesc* D, const Unit* units, int n_units,
         const unsigned pmask = (1u << (a.shift - 1u)) - 1u;
         unsigned long long redges = 0;
         for (long long v = un.v0 + threadIdx.x; v < un.v1; v += blockDim.x) {
-            const long long k = a.key[v];
+            const long long k = a.key[pos_of(a, (unsigned)v)];
             if (is_neg_key(k)) {  // minus infinity (marking mode)
-                a.key[v] = LLONG_MIN;
+                d.dist[v] = LLONG_MIN;
                 redges += (unsigned long long)(a.off[v + 1] - a.off[v]);
                 if (d.pred) d.pred[v] = -1;
                 continue;
             }
             const long long dd = k >> a.shift;
             const bool reached = dd != dmax;
-            a.key[v] = reached ? dd : LLONG_MAX;
+            d.dist[v] = reached ? dd : LLONG_MAX;
             if (reached) redges += (unsigned long long)(a.off[v + 1] - a.off[v]);
             if (d.pred)
                 d.pred[v] = (reached && v != a.src)
@@ -255,6 +415,18 @@ struct sssp_batch {
     unsigned long long* slots;
     unsigned* chunks;
     bq::Ctrl* ctrls;
+    // degree-class key layouts of shared graphs: keys of the queries on
+    // them, remapped targets, positions, original ids, per-tile class counts
+    long long* keys;
+    unsigned* rm_tcol;
+    int* rm_tw;
+    unsigned char* rm_cls;
+    unsigned* rm_pos;
+    unsigned* rm_orig;
+    int* rm_hist;
+    size_t key_cap, rm_cap_m, rm_cap_n, rm_cap_tiles;
+    RemapDesc* d_rm;
+    RemapDesc* h_rm;
     InstDesc* d_desc;
     Unit* d_units;
     int* d_claim;
@@ -285,9 +457,16 @@ struct sssp_batch {
 namespace {
 
 bq_status batch_launch_kernels(sssp_batch* b, int count, int n_units, int n_lists, int grid,
-                               int B) {
+                               int B, int nr, int rm_tiles) {
     hipStream_t s = b->stream;
     const int ug = n_units < 2048 ? n_units : 2048;
+    if (nr > 0) {
+        const int tg = rm_tiles < 4096 ? rm_tiles : 4096;
+        hipLaunchKernelGGL(k_rm_hist, dim3(tg), dim3(64), 0, s, b->d_rm, nr, rm_tiles);
+        hipLaunchKernelGGL(k_rm_scan, dim3(nr), dim3(1024), 0, s, b->d_rm, nr);
+        hipLaunchKernelGGL(k_rm_place, dim3(tg), dim3(64), 0, s, b->d_rm, nr, rm_tiles);
+        hipLaunchKernelGGL(k_rm_rows, dim3(2048), dim3(256), 0, s, b->d_rm, nr);
+    }
     hipLaunchKernelGGL(k_binit, dim3(ug), dim3(BINIT_WG), 0, s, b->d_desc, b->d_units, n_units,
                        b->d_partials, b->d_bc, b->d_reached);
     switch (B) {
@@ -346,7 +525,23 @@ bq_status sssp_batch_create(int32_t max_instances, int64_t max_total_n, int64_t 
     b->chunk_cap = (size_t)(max_total_m / 64 + max_instances);
     b->max_units = (size_t)((max_total_n + max_total_m) / UNIT + 2 * max_instances);
     b->max_claim = (size_t)(8 * 4096 + max_instances + NLIST + 1);
+    // a remapped graph is shared by two or more queries, so the remapped
+    // graphs hold at most half of the vertices and edges of a batch
+    b->key_cap = (size_t)max_total_n;
+    b->rm_cap_n = (size_t)(max_total_n / 2 + 1);
+    b->rm_cap_m = (size_t)(max_total_m / 2 + 1);
+    b->rm_cap_tiles = b->rm_cap_n / RM_TILE + (size_t)max_instances / 2 + 1;
     if (hipMalloc(&b->slots, sizeof(unsigned long long) * b->slot_cap) != hipSuccess ||
+        hipMalloc(&b->keys, sizeof(long long) * b->key_cap) != hipSuccess ||
+        hipMalloc(&b->rm_tcol, sizeof(unsigned) * b->rm_cap_m) != hipSuccess ||
+        hipMalloc(&b->rm_tw, sizeof(int) * b->rm_cap_m) != hipSuccess ||
+        hipMalloc(&b->rm_cls, b->rm_cap_n) != hipSuccess ||
+        hipMalloc(&b->rm_pos, sizeof(unsigned) * b->rm_cap_n) != hipSuccess ||
+        hipMalloc(&b->rm_orig, sizeof(unsigned) * b->rm_cap_n) != hipSuccess ||
+        hipMalloc(&b->rm_hist, sizeof(int) * RM_CLASSES * b->rm_cap_tiles) != hipSuccess ||
+        hipMalloc(&b->d_rm, sizeof(RemapDesc) * max_instances) != hipSuccess ||
+        hipHostMalloc(&b->h_rm, sizeof(RemapDesc) * max_instances, hipHostMallocDefault) !=
+            hipSuccess ||
         hipMalloc(&b->chunks, sizeof(unsigned) * b->chunk_cap) != hipSuccess ||
         hipMalloc(&b->ctrls, sizeof(bq::Ctrl) * max_instances * MAX_Q) != hipSuccess ||
         hipMalloc(&b->d_desc, sizeof(InstDesc) * max_instances) != hipSuccess ||
@@ -392,6 +587,15 @@ bq_status sssp_batch_destroy(sssp_batch* b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->slots) (void)hipFree(b->slots);
     if (b->chunks) (void)hipFree(b->chunks);
+    if (b->keys) (void)hipFree(b->keys);
+    if (b->rm_tcol) (void)hipFree(b->rm_tcol);
+    if (b->rm_tw) (void)hipFree(b->rm_tw);
+    if (b->rm_cls) (void)hipFree(b->rm_cls);
+    if (b->rm_pos) (void)hipFree(b->rm_pos);
+    if (b->rm_orig) (void)hipFree(b->rm_orig);
+    if (b->rm_hist) (void)hipFree(b->rm_hist);
+    if (b->d_rm) (void)hipFree(b->d_rm);
+    if (b->h_rm) (void)hipHostFree(b->h_rm);
     if (b->ctrls) (void)hipFree(b->ctrls);
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_units) (void)hipFree(b->d_units);
@@ -519,6 +723,57 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
             spare -= 2 * extra * caps[k];
         }
     }
+    // Graphs that two or more queries share get the degree-class key layout:
+    // their queries keep keys in the workspace at key positions ordered by
+    // out-degree class, highest first, then by vertex id, so that the keys
+    // most edges point at pack into few cache lines. Queries on a graph of
+    // their own keep their keys in their dist buffers.
+    std::vector<int> rm_of(count, -1);
+    int nr = 0, rm_tiles = 0;
+    {
+        size_t rm_m = 0, rm_n = 0, key_need = 0;
+        std::map<std::tuple<const void*, const void*, const void*, int, long long>,
+                 std::vector<int>> shared;
+        if (!(L.flags & BQ_F_NOREMAP))
+            for (int k = 0; k < count; ++k) {
+                const sssp_instance& x = h_inst[order[k]];
+                shared[std::make_tuple((const void*)x.offsets, (const void*)x.cols,
+                                       (const void*)x.w, x.n, (long long)x.m)]
+                    .push_back(k);
+            }
+        for (auto& kv : shared) {
+            const std::vector<int>& ks = kv.second;
+            if (ks.size() < 2) continue;
+            const sssp_instance& x = h_inst[order[ks[0]]];
+            const int tiles = (x.n + RM_TILE - 1) / RM_TILE;
+            if (rm_m + (size_t)x.m > b->rm_cap_m || rm_n + (size_t)x.n > b->rm_cap_n ||
+                (size_t)(rm_tiles + tiles) > b->rm_cap_tiles ||
+                key_need + (size_t)x.n * ks.size() > b->key_cap)
+                continue;
+            RemapDesc& R = b->h_rm[nr];
+            R.off = (const long long*)x.offsets;
+            R.col = (const int*)x.cols;
+            R.w = (const int*)x.w;
+            R.tcol = b->rm_tcol + rm_m;
+            R.tw = b->rm_tw + rm_m;
+            R.cls = b->rm_cls + rm_n;
+            R.pos = b->rm_pos + rm_n;
+            R.orig = b->rm_orig + rm_n;
+            R.hist = b->rm_hist + (size_t)rm_tiles * RM_CLASSES;
+            R.n = x.n;
+            R.tiles = tiles;
+            R.m = (long long)x.m;
+            R.tile_begin = rm_tiles;
+            R.pad = 0;
+            rm_m += (size_t)x.m;
+            rm_n += (size_t)x.n;
+            rm_tiles += tiles;
+            key_need += (size_t)x.n * ks.size();
+            for (int k : ks) rm_of[k] = nr;
+            ++nr;
+        }
+    }
+    size_t key_off = 0;
     for (int k = 0; k < count; ++k) {
         const int i = order[k];
         const sssp_instance& x = h_inst[i];
@@ -542,7 +797,21 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         a.off = (decltype(a.off))x.offsets;
         a.col = (decltype(a.col))x.cols;
         a.w = (decltype(a.w))x.w;
-        a.key = (decltype(a.key))x.dist;
+        if (rm_of[k] >= 0) {
+            const RemapDesc& R = b->h_rm[rm_of[k]];
+            a.key = (decltype(a.key))(b->keys + key_off);
+            key_off += (size_t)x.n;
+            a.tcol = (decltype(a.tcol))R.tcol;
+            a.tw = (decltype(a.tw))R.tw;
+            a.orig = (decltype(a.orig))R.orig;
+            a.pos = (decltype(a.pos))R.pos;
+        } else {
+            a.key = (decltype(a.key))x.dist;
+            a.tcol = nullptr;
+            a.tw = nullptr;
+            a.orig = nullptr;
+            a.pos = nullptr;
+        }
         a.chunk_owner = (decltype(a.chunk_owner))(b->chunks + chunk_off);
         a.wrange = (decltype(a.wrange))(b->d_partials + 2 * n_units);
         a.n = x.n;
@@ -558,6 +827,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         a.bwd = (L.flags & BQ_F_BWD) ? 1u : 0u;
         a.nseg = nseg;
         a.neginf = (L.flags & BQ_F_NEGINF) ? 1u : 0u;
+        d.dist = (long long*)x.dist;
         d.pred = (int*)x.pred;
         d.orig = i;
         d.unit_begin = n_units;
@@ -622,6 +892,9 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
                               hipMemcpyHostToDevice, s));
     BQ_HIP_TRY(hipMemcpyAsync(b->d_claim, b->h_claim, sizeof(int) * n_claim,
                               hipMemcpyHostToDevice, s));
+    if (nr > 0)
+        BQ_HIP_TRY(hipMemcpyAsync(b->d_rm, b->h_rm, sizeof(RemapDesc) * nr,
+                                  hipMemcpyHostToDevice, s));
     // the caller's stream must be done with the inputs
     BQ_HIP_TRY(hipEventRecord(b->ev_in, cs));
     BQ_HIP_TRY(hipStreamWaitEvent(s, b->ev_in, 0));
@@ -631,7 +904,8 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         const unsigned long long key[8] = {(unsigned long long)count, (unsigned long long)n_units,
                                            (unsigned long long)n_claim, (unsigned long long)grid,
                                            (unsigned long long)B, (unsigned long long)n_lists,
-                                           0, 0};
+                                           (unsigned long long)nr,
+                                           (unsigned long long)rm_tiles};
         if (!b->exec || memcmp(key, b->graph_key, sizeof key) != 0) {
             if (b->exec) {
                 (void)hipGraphExecDestroy(b->exec);
@@ -642,7 +916,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
                 b->graph = nullptr;
             }
             BQ_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            bq_status st = batch_launch_kernels(b, count, n_units, n_lists, grid, B);
+            bq_status st = batch_launch_kernels(b, count, n_units, n_lists, grid, B, nr, rm_tiles);
             hipGraph_t g = nullptr;
             hipError_t ce = hipStreamEndCapture(s, &g);
             if (st != BQ_OK) return st;
@@ -653,7 +927,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         }
         BQ_HIP_TRY(hipGraphLaunch(b->exec, s));
     } else {
-        bq_status st = batch_launch_kernels(b, count, n_units, n_lists, grid, B);
+        bq_status st = batch_launch_kernels(b, count, n_units, n_lists, grid, B, nr, rm_tiles);
         if (st != BQ_OK) return st;
     }
     BQ_HIP_TRY(hipEventRecord(b->ev1, s));
@@ -798,6 +1072,10 @@ bq_status sssp_batch_autotune(sssp_batch* b, int32_t count, const sssp_instance*
         bq_launch t = bestL;
         t.queue_scale = 1;  // queue capacity pow2(n + m/C + 1) instead of twice that
         bq_status st = trial(t);
+        if (st != BQ_OK) return st;
+        t = bestL;
+        t.flags |= BQ_F_NOREMAP;  // keys of shared graphs in vertex order
+        st = trial(t);
         if (st != BQ_OK) return st;
     }
     b->tuned[bucket] = std::make_pair(bestL, best);

@@ -135,7 +135,33 @@ struct SolveArgs {
                                   // (s >= nseg: chunk queue of home s - nseg) has
                                   // slots q.slots + s * q.N, control q.ctrl + s
     unsigned neginf;              // 1: mark minus infinity instead of stopping
+    // Key layout. Null: vertex v's key is key[v] and queue items are vertex
+    // ids. Otherwise (the batched form's degree-class layout of a shared
+    // graph) keys and vertex items are key positions: key position t holds
+    // the key of original vertex orig[t] = v and pos[v] = t. Row offsets and
+    // the parent field of a key stay in original ids; the edges of each row
+    // are read from tcol (target key positions) and tw (weights), in which
+    // every row is reordered by the class of its targets.
+    BQ_GLOBAL const unsigned* tcol;
+    BQ_GLOBAL const int* tw;
+    BQ_GLOBAL const unsigned* orig;
+    BQ_GLOBAL const unsigned* pos;
 };
+
+// original vertex of key position t, and key position of original vertex v
+__device__ __forceinline__ unsigned orig_of(const SolveArgs& a, unsigned t) {
+    return a.orig ? a.orig[t] : t;
+}
+__device__ __forceinline__ unsigned pos_of(const SolveArgs& a, unsigned v) {
+    return a.pos ? a.pos[v] : v;
+}
+// key position of edge e's target, and its weight
+__device__ __forceinline__ int target_of(const SolveArgs& a, long long e) {
+    return a.tcol ? (int)a.tcol[e] : a.col[e];
+}
+__device__ __forceinline__ int weight_of(const SolveArgs& a, long long e) {
+    return a.tw ? a.tw[e] : a.w[e];
+}
 
 constexpr unsigned MAX_SEG = 8;             // gfx950: one segment per XCD
 constexpr unsigned MAX_Q = 2 * MAX_SEG;      // vertex queues + chunk queues
@@ -165,7 +191,8 @@ constexpr int own_cap() { return MAP ? (B <= 128 ? 8192 : 4096) : 0; }
 template <int B, bool MAP = true>
 struct WaveLds {
     unsigned item[B];
-    int u[B];
+    int u[B];          // key position of the item's vertex
+    unsigned pu[B];    // its original id (CSR row, parent field of candidates)
     long long du[B];
     long long eb[B];
     int pre[B + 1];
@@ -277,7 +304,8 @@ __device__ bool flush_vertices(const SolveArgs& a, const Queue& hq, const Queue&
         const int i = c0 + lane;
         const bool live = i < cnt;
         const unsigned v = live ? L.out[i] : 0u;
-        const bool hub = live && a.off[v + 1] - a.off[v] > C;
+        const unsigned ov = live ? orig_of(a, v) : 0u;
+        const bool hub = live && a.off[ov + 1] - a.off[ov] > C;
         const unsigned long long hm = bq::ballot(hub);
         const unsigned long long lm = bq::ballot(live && !hub);
         // compact in place: a light item moves to an index <= its own, and
@@ -312,20 +340,24 @@ __device__ __forceinline__ int find_item(const int* pre, int e, int t) {
     return lo;
 }
 
-// parent field of x's key; the none sentinel for unreached and minus-infinity
+// key position of the parent named in x's key (x a key position); the none
+// sentinel for unreached and minus-infinity
 __device__ __forceinline__ unsigned parent_of(const SolveArgs& a, int x) {
     const long long k = bq::ld_rlx(&a.key[x]);
     const unsigned long long mask = (1ull << (a.shift - 1u)) - 1ull;
     if (is_neg_key(k)) return (unsigned)mask;
-    return (unsigned)(((unsigned long long)k >> 1) & mask);
+    const unsigned p = (unsigned)(((unsigned long long)k >> 1) & mask);
+    return p == (unsigned)mask ? p : pos_of(a, p);
 }
 
-// minimum weight over edges p -> y (whole wave scans row p); LLONG_MAX if none
+// minimum weight over edges p -> y, p and y key positions (whole wave scans
+// p's row); LLONG_MAX if none
 __device__ long long min_edge(const SolveArgs& a, unsigned p, unsigned y) {
-    const long long s = a.off[p], e = a.off[p + 1];
+    const unsigned pr = orig_of(a, p);
+    const long long s = a.off[pr], e = a.off[pr + 1];
     long long best = LLONG_MAX;
     for (long long i = s + bq::lane_id(); i < e; i += 64)
-        if ((unsigned)a.col[i] == y && a.w[i] < best) best = a.w[i];
+        if ((unsigned)target_of(a, i) == y && weight_of(a, i) < best) best = weight_of(a, i);
     for (int off = 32; off > 0; off >>= 1) {
         const long long o = __shfl_xor(best, off, 64);
         best = o < best ? o : best;
@@ -656,14 +688,16 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
             if (i < e) {
                 const unsigned it = L.item[i];
                 int u;
+                unsigned ur;
                 long long d, s, t;
                 if (it < n) {
                     u = (int)it;
                     const long long old = __hip_atomic_fetch_and(
                         &a.key[u], ~1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     d = old >> shift;
-                    s = a.off[u];
-                    t = a.off[u + 1];
+                    ur = orig_of(a, (unsigned)u);
+                    s = a.off[ur];
+                    t = a.off[ur + 1];
                     if (t - s > C) {
                         const long long js = s >> clog, je = (t - 1) >> clog;
                         t = (js + 1) << clog;
@@ -673,13 +707,15 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
                     const long long j = (long long)(it - n);
                     u = (int)bq::ld_rlx(&a.chunk_owner[j]);
                     d = bq::ld_rlx(&a.key[u]) >> shift;
-                    const long long r0 = a.off[u], r1 = a.off[u + 1];
+                    ur = orig_of(a, (unsigned)u);
+                    const long long r0 = a.off[ur], r1 = a.off[ur + 1];
                     s = j << clog;
                     t = (j + 1) << clog;
                     s = s > r0 ? s : r0;
                     t = t < r1 ? t : r1;
                 }
                 L.u[i] = u;
+                L.pu[i] = ur;
                 L.du[i] = d;
                 L.eb[i] = s;
                 cnt = (int)(t - s);
@@ -763,8 +799,8 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
                     const int idx = t < mapped ? (int)L.own[t] : find_item(L.pre, (int)e, t);
                     const long long edge = L.eb[idx] + (t - L.pre[idx]);
                     aidx[r] = idx;
-                    av[r] = a.col[edge];
-                    aw[r] = a.w[edge];
+                    av[r] = target_of(a, edge);
+                    aw[r] = weight_of(a, edge);
                 }
             }
         };
@@ -794,7 +830,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
                 valid[r] = tv[r] >= 0;
                 seen[r] = bkey[r];
                 cd[r] = L.du[bidx[r]] + (long long)bw[r];
-                cand[r] = pack_key(cd[r], (unsigned)L.u[bidx[r]], shift);
+                cand[r] = pack_key(cd[r], L.pu[bidx[r]], shift);
                 // marking mode: a candidate below the certain lower bound (or
                 // from a minus-infinity source, whose label is far below it)
                 // proves that a negative cycle reaches the target

@@ -296,3 +296,48 @@ def test_many_small_queries_on_few_workgroups(batch, wgs):
         items.append((g, int(i * 7919 % g.n), upload(g)))
     qs, keep = make_queries(items)
     check_all(qs, keep, batch.solve(qs, launch={"wg_count": wgs}))
+
+
+@pytest.mark.parametrize("flags", [0, pkg.BQ_F_NOREMAP], ids=["remapped", "vertex_order"])
+def test_shared_graphs_mixed_with_own(batch, flags):
+    """Queries that share a graph (several per graph: RMAT with hubs and
+    split rows, a mesh, a graph with a planted negative cycle) next to
+    queries on graphs of their own. Shared graphs get the degree-class key
+    layout unless BQ_F_NOREMAP; every answer, flag and predecessor must be
+    the oracle's either way."""
+    rm = synth.rmat(14, 16, seed=31)
+    mesh = synth.road(40, plant_cycle=False, seed=32)
+    cyc = synth.road(24, plant_cycle=True, seed=33)
+    pr = synth.potential_random(4000, 30000, seed=34)
+    t_rm, t_mesh, t_cyc, t_pr = upload(rm), upload(mesh), upload(cyc), upload(pr)
+    items = [(rm, int(s), t_rm) for s in synth.random_sources(rm, 5, seed=35)]
+    items += [(mesh, int(s), t_mesh) for s in (0, 17, 1599)]
+    items += [(cyc, int(s), t_cyc) for s in (0, 300)]
+    items += [(pr, 11, t_pr), (pr, 2222, t_pr)]
+    items += [(synth.erdos_renyi(3000 + 500 * i, 8, seed=36 + i), 1 + i, None) for i in range(4)]
+    items = [(g, s, t if t is not None else upload(g)) for g, s, t in items]
+    qs, keep = make_queries(items)
+    print(f"[batched] shared graphs, flags={flags}", flush=True)
+    for graph in (False, True):
+        for q in qs:
+            q[4].fill_(-3)
+        check_all(qs, keep, batch.solve(qs, launch={"flags": flags}, graph=graph))
+
+
+@pytest.mark.parametrize("flags", [0, pkg.BQ_F_NOREMAP], ids=["remapped", "vertex_order"])
+def test_shared_graph_minus_infinity(batch, flags):
+    """Marking mode on a shared graph with a reachable negative cycle: the
+    minus-infinity vertices and the exact labels of the rest match the
+    oracle for every query (the cycle search walks parents through the key
+    layout)."""
+    g = synth.road(32, plant_cycle=True, seed=41)
+    t = upload(g)
+    srcs = [0, 5, 517, 1023]
+    qs, keep = make_queries([(g, s, t) for s in srcs])
+    neg = batch.solve(qs, launch={"flags": flags | pkg.BQ_F_NEGINF})
+    torch.cuda.synchronize()
+    for (off, col, w, src, dist, pred), flag in zip(qs, neg):
+        d_ref, p_ref, neg_ref = oracle.neg_inf(g, src)
+        assert flag == neg_ref
+        assert np.array_equal(dist.cpu().numpy(), d_ref)
+        assert np.array_equal(pred.cpu().numpy(), p_ref)
