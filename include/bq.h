@@ -87,6 +87,16 @@ typedef struct {
                              BQ_F_TRACE. bq_bench_mixed / bq_bench_enqdeq:
                              1, 2, 4 or 8 segments of capacity/segments
                              slots (0 = 1). Other calls ignore it. */
+    int32_t bucket_width; /* sssp_bf, sssp_bf_noalloc: 0 = every home segment
+                             keeps one FIFO of improved vertices (the method as
+                             the paper runs it); k > 0 = near / far buckets: a
+                             vertex whose new label is at or above a threshold
+                             T goes to a far queue that waves take only when
+                             no near work is queued, and a far batch moves T
+                             to its smallest label + k * max(1, max |w|).
+                             Same results, fewer relabels on large-diameter
+                             graphs; the autotuner tries it. Needs one more
+                             queue per segment. Other calls ignore it. */
 } bq_launch;
 
 #define BQ_F_VALIDATE 1u  /* sssp_bf: check the CSR on the device first */
@@ -293,12 +303,16 @@ bq_status sssp_bf_noalloc(int32_t n, int64_t m, const int64_t* d_offsets, const 
                           const int32_t* d_w, int32_t src, int64_t* d_dist, int32_t* d_pred,
                           int32_t* h_neg_cycle, const bq_launch* launch, void* stream);
 
-/* Autotuner: time sssp_bf on this input (d_dist is used as scratch) for
- * workgroup counts 4, 8, 16, ... up to the co-resident maximum (stopping
+/* Autotuner: time sssp_bf on this input (d_dist is used as scratch). Unless
+ * base->bucket_width is set, a few runs at the default grid with and without
+ * near / far buckets first pick the order of work (buckets when they are at
+ * least 20 % faster); then, in that family: workgroup counts 4, 8, 16, ...
+ * up to the co-resident maximum (stopping
  * once clearly past the fastest) and 3/4 and 3/2 of the fastest, then
  * ticket batches b = 2, 4 around the
  * fastest count, then row chunks 64 and 256 at the fastest shape, then
- * 1, 2 and 4 queue segments against the default; `reps` runs per candidate
+ * 1, 2 and 4 queue segments against the default, and with buckets bucket
+ * widths 2 and 4; `reps` runs per candidate
  * (0 = 5), compared by their median, a candidate replacing the fastest so
  * far only when at least 3 % faster; a winner that differs from the best
  * power-of-two count with default settings is finally run against it,
@@ -515,6 +529,13 @@ bq_status bq_server_set_small_lanes(bq_server* s, int32_t k);
  * while the server lives); returns its id. */
 bq_status bq_server_add_graph(bq_server* s, int32_t n, int64_t m, const int64_t* d_offsets,
                               const int32_t* d_cols, const int32_t* d_w, int32_t* graph_id);
+
+/* Give the large requests on resident graph graph_id (those launched alone:
+ * work for 64 or more workgroups, (n + m/16) / 16384 >= 64) a launch of their
+ * own instead of the server's, e.g. one found by sssp_autotune for that graph
+ * (near / far buckets for a road mesh). NULL restores the server's launch.
+ * BQ_EINVAL for an unknown graph id; no device work. */
+bq_status bq_server_set_graph_launch(bq_server* s, int32_t graph_id, const bq_launch* launch);
 
 /* Replay `count` requests at their arrival times on the calling thread:
  * arrived requests wait in arrival order; a request is admitted when its

@@ -36,7 +36,7 @@ EXPORTS = [
     "sssp_last_trace", "sssp_autotune", "sssp_batch_create", "sssp_batch_destroy",
     "sssp_bf_batched", "sssp_batch_last_stats", "sssp_batch_autotune",
     "sssp_bf_batched_start", "sssp_batch_finish", "bq_server_create", "bq_server_destroy",
-    "bq_server_set_small_lanes", "bq_server_add_graph", "bq_server_run", "bq_arena_create", "bq_arena_destroy",
+    "bq_server_set_small_lanes", "bq_server_set_graph_launch", "bq_server_add_graph", "bq_server_run", "bq_arena_create", "bq_arena_destroy",
     "bq_arena_alloc", "bq_arena_free", "bq_arena_usage",
     "bq_strerror", "bq_device_cus", "bq_probe",
     "sssp_rounds_create", "sssp_rounds_destroy", "sssp_bf_rounds", "sssp_rounds_last_stats",
@@ -54,7 +54,8 @@ class Launch(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("wg_count", ctypes.c_int32),
                 ("ticket_batch", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("timeout_us", ctypes.c_uint64), ("row_chunk", ctypes.c_int32),
-                ("queue_scale", ctypes.c_int32), ("segments", ctypes.c_int32)]
+                ("queue_scale", ctypes.c_int32), ("segments", ctypes.c_int32),
+                ("bucket_width", ctypes.c_int32)]
 
 
 class BenchStats(ctypes.Structure):
@@ -161,6 +162,7 @@ def lib(path: str | None = None):
         "bq_server_destroy": ([vp], i32),
         "bq_server_set_small_lanes": ([vp, i32], i32),
         "bq_server_add_graph": ([vp, i32, i64, vp, vp, vp, P(i32)], i32),
+        "bq_server_set_graph_launch": ([vp, i32, P(Launch)], i32),
         "bq_server_run": ([vp, i32, P(Request), P(Response), P(ServerStats)], i32),
         "bq_arena_create": ([u64, u64, P(vp)], i32),
         "bq_arena_destroy": ([vp], i32),
@@ -511,6 +513,12 @@ class Server:
                                          _ptr(w), ctypes.byref(gid)), "bq_server_add_graph")
         self._graphs.append((offsets, cols, w))
         return gid.value
+
+    def set_graph_launch(self, graph_id: int, launch=None):
+        """bq_server_set_graph_launch: large requests on this resident graph
+        run with `launch` (a dict or Launch); None restores the default."""
+        _check(lib().bq_server_set_graph_launch(self.handle, int(graph_id), _launch(launch)),
+               "bq_server_set_graph_launch")
 
     def run(self, requests):
         """requests: list of dicts with arrival_us, src, and either graph=<id>

@@ -52,6 +52,7 @@ struct Ctrl {
     Word error;      // ERR_* of the first failure
     Word negcycle;   // solver: 1 when a negative cycle was proved
     Word aux[6];     // solver scratch: weight range, dequeue base and clock at start
+    Word busy;       // solver with near / far buckets: near items taken, not yet retired
     Word stats[ST_N];
 };
 

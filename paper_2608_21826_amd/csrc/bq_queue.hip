@@ -249,6 +249,7 @@ Launch resolve(const bq_launch* l, int default_wgs) {
     r.batch = (l && l->ticket_batch > 0) ? l->ticket_batch : 1;
     r.row_chunk = (l && l->row_chunk > 0) ? l->row_chunk : 0;
     r.segments = (l && l->segments > 0) ? l->segments : 0;
+    r.bucket_width = l ? l->bucket_width : 0;
     r.flags = l ? l->flags : 0u;
     const unsigned long long us = (l && l->timeout_us) ? l->timeout_us : 2000000ull;
     r.limit = us * 100ull;  // 100 MHz

@@ -28,6 +28,7 @@ struct Launch {
     int batch;                 // ticket_batch b
     int row_chunk;             // solver row chunk (edges)
     int segments;              // solver queue segments (0 = default)
+    int bucket_width;          // solver near / far buckets (0 = off)
     uint32_t flags;
     unsigned long long limit;  // watchdog, 100 MHz ticks
 };

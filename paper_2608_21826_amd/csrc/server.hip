@@ -50,6 +50,8 @@ struct ResidentGraph {
     const int64_t* off;
     const int32_t* col;
     const int32_t* w;
+    bool has_launch;   // large requests on this graph use `launch`
+    bq_launch launch;
 };
 
 struct Lane {
@@ -151,8 +153,16 @@ bq_status bq_server_add_graph(bq_server* s, int32_t n, int64_t m, const int64_t*
     if (!s || !graph_id || n < 1 || m < 0 || !d_offsets || (m > 0 && (!d_cols || !d_w)))
         return BQ_EINVAL;
     if (n > s->max_batch_n || m > s->max_batch_m) return BQ_EBUSY;
-    s->graphs.push_back(ResidentGraph{n, m, d_offsets, d_cols, d_w});
+    s->graphs.push_back(ResidentGraph{n, m, d_offsets, d_cols, d_w, false, bq_launch{}});
     *graph_id = (int32_t)s->graphs.size() - 1;
+    return BQ_OK;
+}
+
+bq_status bq_server_set_graph_launch(bq_server* s, int32_t graph_id, const bq_launch* launch) {
+    if (!s || graph_id < 0 || graph_id >= (int32_t)s->graphs.size()) return BQ_EINVAL;
+    ResidentGraph& g = s->graphs[graph_id];
+    g.has_launch = launch != nullptr;
+    g.launch = launch ? *launch : bq_launch{};
     return BQ_OK;
 }
 
@@ -339,6 +349,14 @@ bq_status bq_server_run(bq_server* s, int32_t count, const bq_request* reqs,
             L.neg.assign(inst.size(), 0);
             L.reached.assign(inst.size(), 0);
             bq_launch lo = s->launch;
+            // a large request on a resident graph with a launch of its own
+            // (launched alone) runs with that launch
+            if (inst.size() == 1) {
+                const bq_request& r0 = reqs[L.reqs[0]];
+                if (r0.graph >= 0 && s->graphs[r0.graph].has_launch &&
+                    ((long long)need[L.reqs[0]].n + need[L.reqs[0]].m / 16) / 16384 >= LARGE_WGS)
+                    lo = s->graphs[r0.graph].launch;
+            }
             bq_status st = sssp_bf_batched_start(L.batch, (int32_t)inst.size(), inst.data(), &lo,
                                                  L.stream);
             if (st != BQ_OK) {

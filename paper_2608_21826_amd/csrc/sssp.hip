@@ -234,6 +234,33 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
         }
         return BQ_OK;
     };
+    // Order of work: one FIFO per home (the method as the paper runs it) or
+    // near / far buckets. One series of each at the default grid picks the
+    // family the rest of the search tunes: on a large-diameter graph the
+    // buckets save most relabels, on a power-law graph they only add work.
+    if (L.bucket_width == 0) {
+        const int g0 = default_grid(n, (long long)m, max_grid);
+        std::vector<double> med(2);
+        for (int fam = 0; fam < 2; ++fam) {
+            bq_launch t = L;
+            t.wg_count = g0;
+            t.bucket_width = fam;
+            std::vector<double> ts;
+            for (int r = 0; r < (reps < 3 ? reps : 3); ++r) {
+                int32_t neg = 0;
+                bq_status st = sssp_bf(c, n, m, d_offsets, d_cols, d_w, src, d_dist, nullptr,
+                                       &neg, &t, stream);
+                if (st != BQ_OK) return st;
+                ts.push_back(c->last.ms);
+            }
+            std::sort(ts.begin(), ts.end());
+            med[fam] = ts[ts.size() / 2];
+        }
+        if (med[1] < 0.8 * med[0]) {
+            L.bucket_width = 1;
+            bestL = L;
+        }
+    }
     // workgroup count: powers of two upwards until clearly past the minimum
     int best_wgs = 4;
     for (int wgs = 4; wgs <= max_grid; wgs *= 2) {
@@ -285,6 +312,18 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
             bq_status st = trial(cur.wg_count, cur.ticket_batch, &ms, cur.row_chunk, seg);
             if (st != BQ_OK) return st;
         }
+    }
+    // bucket widths 2 and 4 (threshold steps of 2 or 4 max |w|) at the best
+    // shape, for the bucket family
+    if (bestL.bucket_width > 0) {
+        const bq_launch cur = bestL;
+        for (int bw : {2, 4}) {
+            L.bucket_width = bw;
+            double ms = 0;
+            bq_status st = trial(cur.wg_count, cur.ticket_batch, &ms, cur.row_chunk, cur.segments);
+            if (st != BQ_OK) return st;
+        }
+        L.bucket_width = cur.bucket_width;
     }
     // confirmation: the winner against the best power-of-two count with
     // default settings, alternating runs, so that one lucky series cannot
@@ -376,6 +415,7 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     int nseg = L.segments > 0 ? L.segments : (grid < (int)MAX_SEG ? grid : (int)MAX_SEG);
     if (nseg > (int)MAX_SEG) return BQ_EINVAL;
     if (L.flags & BQ_F_TRACE) nseg = 1;  // the timeline follows one queue
+    if (L.bucket_width < 0) return BQ_EINVAL;
     const unsigned shift = key_shift(n);
     SolveArgs a;
     a.q = q;
@@ -397,6 +437,8 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     a.trace_cap = TRACE_CAP;
     a.bwd = (L.flags & BQ_F_BWD) ? 1u : 0u;
     a.nseg = (unsigned)nseg;
+    a.bucket_width = L.bucket_width;
+    a.nq = (L.bucket_width > 0 ? 3u : 2u) * (unsigned)nseg;
     a.neginf = (L.flags & BQ_F_NEGINF) ? 1u : 0u;
     a.tcol = nullptr;
     a.tw = nullptr;
@@ -586,10 +628,12 @@ extern "C" bq_status sssp_bf_noalloc(int32_t n, int64_t m, const int64_t* d_offs
     if (grid > max_grid) grid = max_grid;
     int nseg = L.segments > 0 ? L.segments : (grid < (int)MAX_SEG ? grid : (int)MAX_SEG);
     if (nseg > (int)MAX_SEG) return BQ_EINVAL;
+    if (L.bucket_width < 0) return BQ_EINVAL;
+    const unsigned nq = (L.bucket_width > 0 ? 3u : 2u) * (unsigned)nseg;
 
     // layout of this call in the scratch array: control blocks of all MAX_Q
     // queues (k_init reads every block), weight-range partials, chunk
-    // table, then the slots of the 2 * nseg queues it uses (each sized as in
+    // table, then the slots of the nq queues it uses (each sized as in
     // sssp_ctx_create: 2 * pow2(n + m / 64 + 1), at least 4096)
     const unsigned long long need =
         (unsigned long long)n + ((unsigned long long)m >> MIN_CHUNK_LOG) + 1ull;
@@ -599,7 +643,7 @@ extern "C" bq_status sssp_bf_noalloc(int32_t n, int64_t m, const int64_t* d_offs
     const unsigned long long wr_bytes = round256(sizeof(int) * 2 * INIT_MAX_BLOCKS);
     const unsigned long long ch_bytes =
         round256(sizeof(unsigned) * (((unsigned long long)m >> clog) + 1ull));
-    const unsigned long long slot_words = 2ull * (unsigned long long)nseg * cap;
+    const unsigned long long slot_words = (unsigned long long)nq * cap;
     const unsigned long long total = ctrl_bytes + wr_bytes + ch_bytes + 8ull * slot_words;
     if (cap > (1ull << 31) || total > NOALLOC_SCRATCH_BYTES) return BQ_EBUSY;
     bq::Ctrl* ctrl = (bq::Ctrl*)base;
@@ -656,6 +700,8 @@ extern "C" bq_status sssp_bf_noalloc(int32_t n, int64_t m, const int64_t* d_offs
     a.trace_cap = 0;
     a.bwd = (L.flags & BQ_F_BWD) ? 1u : 0u;
     a.nseg = (unsigned)nseg;
+    a.bucket_width = L.bucket_width;
+    a.nq = (L.bucket_width > 0 ? 3u : 2u) * (unsigned)nseg;
     a.neginf = (L.flags & BQ_F_NEGINF) ? 1u : 0u;
     a.tcol = nullptr;
     a.tw = nullptr;

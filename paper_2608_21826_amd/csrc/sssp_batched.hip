@@ -268,8 +268,10 @@ __global__ __launch_bounds__(BINIT_WG) void k_binit(const InstDesc* D, const Uni
                 c->error.v = 0ull;
                 c->negcycle.v = 0ull;
                 c->aux[0].v = (unsigned long long)(d.unit_end - d.unit_begin);
-                for (unsigned sg = 0; sg < 2 * a.nseg; ++sg)  // dequeue positions at start
+                for (unsigned sg = 0; sg < a.nq; ++sg)  // dequeue positions at start
                     c[sg].aux[2].v = c[sg].head.v;
+                c->aux[1].v = (unsigned long long)LLONG_MIN;  // near / far threshold
+                c->busy.v = 0ull;
                 c->aux[4].v = bq::now_ticks();
                 c->aux[5].v = 0ull;  // finished flag
                 for (int i = 0; i < bq::ST_N; ++i) c->stats[i].v = 0ull;
@@ -520,8 +522,8 @@ bq_status sssp_batch_create(int32_t max_instances, int64_t max_total_n, int64_t 
     b->max_m = max_total_m;
     // per query: capacity pow2(scale * (n + m/C + 1)) with scale <= 2 and
     // C >= 64, at least 4096 -> at most 4 * (n + m/64 + 1) + 4096 each
-    b->slot_cap = 2 * ((size_t)(4 * (max_total_n + max_total_m / 64 + max_instances)) +
-                       (size_t)max_instances * 4096);  // vertex queue + chunk lane
+    b->slot_cap = 3 * ((size_t)(4 * (max_total_n + max_total_m / 64 + max_instances)) +
+                       (size_t)max_instances * 4096);  // vertex queue, chunk lane, far queue
     b->chunk_cap = (size_t)(max_total_m / 64 + max_instances);
     b->max_units = (size_t)((max_total_n + max_total_m) / UNIT + 2 * max_instances);
     b->max_claim = (size_t)(8 * 4096 + max_instances + NLIST + 1);
@@ -641,6 +643,9 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
     }
     const int scale = (launch && launch->queue_scale > 0) ? launch->queue_scale : 2;
     if (scale > 2) return BQ_EINVAL;
+    if (L.bucket_width < 0) return BQ_EINVAL;
+    // queues per segment: vertex queue and chunk lane, plus a far queue with buckets
+    const unsigned qps = L.bucket_width > 0 ? 3u : 2u;
     // validate and order by work, biggest first
     long long tot_n = 0, tot_m = 0;
     std::vector<int> order(count);
@@ -710,17 +715,17 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
             unsigned long long cap = pow2ceil((unsigned long long)scale * need);
             if (cap < 4096ull) cap = 4096ull;
             caps[k] = cap;
-            base += 2 * cap;
+            base += qps * cap;
         }
         unsigned long long spare = base < b->slot_cap ? b->slot_cap - base : 0ull;
         for (int k = 0; k < count; ++k) {
             const sssp_instance& x = h_inst[order[k]];
             const long long units = (long long)x.n + x.m / 16;
             if (units / 16384 < 16 || confined[k]) continue;
-            unsigned long long extra = spare / (2 * caps[k]);
+            unsigned long long extra = spare / (qps * caps[k]);
             if (extra > MAX_SEG - 1) extra = MAX_SEG - 1;
             nsegs[k] = 1u + (unsigned)extra;
-            spare -= 2 * extra * caps[k];
+            spare -= qps * extra * caps[k];
         }
     }
     // Graphs that two or more queries share get the degree-class key layout:
@@ -782,7 +787,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         const size_t chunks = (size_t)((unsigned long long)x.m >> clog) + 1;
         const long long big = x.n > x.m ? x.n : x.m;
         const int ku = (int)((big + UNIT - 1) / UNIT);
-        if (slot_off + 2 * nseg * cap > b->slot_cap || chunk_off + chunks > b->chunk_cap ||
+        if (slot_off + qps * nseg * cap > b->slot_cap || chunk_off + chunks > b->chunk_cap ||
             (size_t)(n_units + ku) > b->max_units)
             return BQ_EBUSY;
         InstDesc& d = b->h_desc[k];
@@ -826,6 +831,8 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         a.trace_cap = 0;
         a.bwd = (L.flags & BQ_F_BWD) ? 1u : 0u;
         a.nseg = nseg;
+        a.nq = qps * nseg;
+        a.bucket_width = L.bucket_width;
         a.neginf = (L.flags & BQ_F_NEGINF) ? 1u : 0u;
         d.dist = (long long*)x.dist;
         d.pred = (int*)x.pred;
@@ -860,7 +867,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         layout.push_back(cap);
         layout.push_back(slot_off);
         layout.push_back(nseg);
-        slot_off += 2 * nseg * cap;  // vertex queues and their chunk lanes
+        slot_off += qps * nseg * cap;  // vertex queues, chunk lanes (and far queues)
         chunk_off += chunks;
     }
     // the claim array: list offsets, then the lists one after another

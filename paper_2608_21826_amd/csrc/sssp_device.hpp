@@ -111,6 +111,10 @@ constexpr int OUTCAP = 1024;  // LDS push buffer per wave
 #define SSSP_MIN_WAVES 2
 #endif
 constexpr int U = SSSP_UNROLL;  // edges per lane per pipelined step
+// near / far buckets: far work is taken only while at most this many near
+// items per wave of the grid are in flight (half a batch): waiting for none
+// leaves most waves idle, never waiting lets the far queues run ahead
+constexpr unsigned long long FAR_GATE_PER_WAVE = 32;
 
 struct SolveArgs {
     Queue q;
@@ -131,9 +135,15 @@ struct SolveArgs {
     unsigned trace_shift;         // one sample per 2^trace_shift dequeued items
     unsigned trace_cap;           // samples
     unsigned bwd;                 // dequeue broker policy: 0 Broker Queue, 1 BWD
-    unsigned nseg;                // queue segments, 1..MAX_SEG; queue s < 2 nseg
-                                  // (s >= nseg: chunk queue of home s - nseg) has
-                                  // slots q.slots + s * q.N, control q.ctrl + s
+    unsigned nseg;                // queue segments, 1..MAX_SEG; queue s < nq
+                                  // (s < nseg: vertex queue of home s; s < 2 nseg:
+                                  // chunk queue of home s - nseg; s < 3 nseg: far
+                                  // queue of home s - 2 nseg) has slots
+                                  // q.slots + s * q.N, control q.ctrl + s
+    unsigned nq;                  // queues in use: 2 nseg, or 3 nseg with buckets
+    long long bucket_width;       // 0: one FIFO per home; k > 0: near / far split at
+                                  // a threshold T that advances in steps of
+                                  // k * max(1, max |w|) (see solve_instance)
     unsigned neginf;              // 1: mark minus infinity instead of stopping
     // Key layout. Null: vertex v's key is key[v] and queue items are vertex
     // ids. Otherwise (the batched form's degree-class layout of a shared
@@ -164,7 +174,8 @@ __device__ __forceinline__ int weight_of(const SolveArgs& a, long long e) {
 }
 
 constexpr unsigned MAX_SEG = 8;             // gfx950: one segment per XCD
-constexpr unsigned MAX_Q = 2 * MAX_SEG;      // vertex queues + chunk queues
+constexpr unsigned MAX_Q = 3 * MAX_SEG;      // vertex queues + chunk queues + far queues
+constexpr unsigned FAR_BIT = 0x80000000u;    // in the push buffer: vertex goes to the far queue
 
 // view of queue segment s (segment 0's control block holds the global words:
 // pending, abort, error, negcycle, stats)
@@ -290,34 +301,46 @@ __device__ bool flush_out(const SolveArgs& a, const Queue& seg, const unsigned* 
     return true;
 }
 
-// Publish the wave's improved vertices (L.out[0, cnt)): with `route`, those
-// with rows longer than one chunk go to the chunk lane `cq`, the rest to the
-// vertex queue `hq`.
+// Publish the wave's improved vertices (L.out[0, cnt)): entries marked
+// FAR_BIT go to the far queue `fq`; with `route`, those with rows longer than
+// one chunk go to the chunk lane `cq`; the rest to the vertex queue `hq`.
 template <class LDS>
-__device__ bool flush_vertices(const SolveArgs& a, const Queue& hq, const Queue& cq, LDS& L,
-                               int cnt, bool route, long long& debt, unsigned long long& spins) {
-    if (!route || cnt == 0) return flush_out(a, hq, L.out, cnt, debt, false, spins);
+__device__ bool flush_vertices(const SolveArgs& a, const Queue& hq, const Queue& cq,
+                               const Queue& fq, LDS& L, int cnt, bool route, long long& debt,
+                               unsigned long long& spins) {
+    if ((!route && !a.bucket_width) || cnt == 0)
+        return flush_out(a, hq, L.out, cnt, debt, false, spins);
     const int lane = bq::lane_id();
     const long long C = 1ll << a.chunk_log;
-    int nl = 0, nh = 0;
+    int nl = 0, nh = 0, nf = 0;
     for (int c0 = 0; c0 < cnt; c0 += 64) {
         const int i = c0 + lane;
         const bool live = i < cnt;
-        const unsigned v = live ? L.out[i] : 0u;
-        const unsigned ov = live ? orig_of(a, v) : 0u;
-        const bool hub = live && a.off[ov + 1] - a.off[ov] > C;
+        const unsigned x = live ? L.out[i] : 0u;
+        const unsigned v = x & ~FAR_BIT;
+        const bool far = live && (x & FAR_BIT) != 0u;
+        bool hub = false;
+        if (route && live && !far) {
+            const unsigned ov = orig_of(a, v);
+            hub = a.off[ov + 1] - a.off[ov] > C;
+        }
         const unsigned long long hm = bq::ballot(hub);
-        const unsigned long long lm = bq::ballot(live && !hub);
+        const unsigned long long fm = bq::ballot(far);
+        const unsigned long long lm = bq::ballot(live && !hub && !far);
         // compact in place: a light item moves to an index <= its own, and
-        // every lane has read its item before any lane writes
-        if (live && !hub) L.out[nl + bq::rank_in(lm)] = v;
+        // every lane has read its item before any lane writes; hubs fill
+        // L.hv from the front, far items from the back (nh + nf <= cnt)
+        if (live && !hub && !far) L.out[nl + bq::rank_in(lm)] = v;
         if (hub) L.hv[nh + bq::rank_in(hm)] = v;
+        if (far) L.hv[OUTCAP - 1 - (nf + bq::rank_in(fm))] = v;
         nl += __popcll(lm);
         nh += __popcll(hm);
+        nf += __popcll(fm);
     }
     __builtin_amdgcn_wave_barrier();
     if (!flush_out(a, hq, L.out, nl, debt, false, spins)) return false;
-    return flush_out(a, cq, L.hv, nh, debt, false, spins);
+    if (!flush_out(a, cq, L.hv, nh, debt, false, spins)) return false;
+    return flush_out(a, fq, L.hv + (OUTCAP - nf), nf, debt, false, spins);
 }
 
 // Give the wave's debt back to pending (before it waits for work).
@@ -444,16 +467,23 @@ __device__ int idle_wait(const SolveArgs& a, WgShared& S, int wid, unsigned long
             while (true) {
                 ++polls;
                 // lane s < nseg watches segment s; progress = sum of heads
-                unsigned long long pend = 0, hd = 0;
+                unsigned long long pend = 0, hd = 0, busy = 0;
                 long long cnt = 0;
-                if ((unsigned)lane < 2u * a.nseg) {
+                if ((unsigned)lane < a.nq) {
                     const bq::Ctrl* c = q.ctrl + lane;
                     cnt = bq::ld_rlx((BQ_GLOBAL const long long*)(&c->count.v));
                     hd = bq::ld_rlx(&c->head.v);
                 }
                 if (lane == 0) pend = bq::ld_rlx(&q.ctrl->pending.v);
+                if (lane == 1 && a.bucket_width) busy = bq::ld_rlx(&q.ctrl->busy.v);
                 pend = bq::bcast64(pend);
-                const bool items = __any(cnt > 0);
+                busy = (unsigned long long)__shfl((long long)busy, 1, 64);
+                // with buckets, far items are work only once no near batch is
+                // in flight (the order the far queues are meant to keep)
+                const bool far_lane = (unsigned)lane >= 2u * a.nseg;
+                const unsigned long long gate =
+                    FAR_GATE_PER_WAVE * gridDim.x * (unsigned long long)(blockDim.x >> 6);
+                const bool items = __any(cnt > 0 && (!far_lane || busy <= gate));
                 for (int off = 32; off > 0; off >>= 1) hd += __shfl_xor(hd, off, 64);
                 if (pend == 0ull) {
                     if (lane == 0) {
@@ -555,8 +585,9 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
     const unsigned home = blockIdx.x % a.nseg;
     const Queue hq = seg_queue(a, home);
     const Queue cq = seg_queue(a, a.nseg + home);  // the chunk lane of this home
+    const Queue fq = seg_queue(a, 2u * a.nseg + home);  // its far queue (buckets only)
     const unsigned long long head0_lane =
-        (unsigned)lane < 2u * a.nseg ? bq::ld_rlx(&(q.ctrl + lane)->aux[2].v) : 0ull;
+        (unsigned)lane < a.nq ? bq::ld_rlx(&(q.ctrl + lane)->aux[2].v) : 0ull;
     long long maxabs = 0;
     if (a.m > 0) {
         maxabs = wmax > -wmin ? wmax : -wmin;
@@ -570,6 +601,17 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
         return -1;
     }
     const long long lbound = (long long)(a.n - 1) * (wmin < 0 ? wmin : 0ll);
+    // Near / far buckets (bucket_width k > 0): a pushed vertex whose new
+    // label is below the threshold T goes to its home's vertex queue, the
+    // others to the far queue. Waves take far work only when no vertex or
+    // chunk queue has items and few near items are in flight (the `busy`
+    // word); the smallest label of a far batch then moves T up to that
+    // label + k * max(1, max |w|). Processing roughly in label order cuts
+    // the relabels of large-diameter graphs; the order of work never
+    // changes the result.
+    const long long bdelta = a.bucket_width * (maxabs > 1 ? maxabs : 1ll);
+    const unsigned long long far_gate =
+        FAR_GATE_PER_WAVE * gridDim.x * (unsigned long long)(blockDim.x >> 6);
     const unsigned long long suspect_after = 4ull * (unsigned long long)a.n +
                                              4ull * (unsigned long long)(a.m >> clog) + 4096ull;
     const unsigned long long walk_stride =
@@ -629,9 +671,49 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
                 e = bq::bcast32(e);
             }
         }
+        bool far_ok = false;
+        if (e == 0 && a.bucket_width) {
+            unsigned long long busy = 0;
+            if (lane == 0) busy = bq::ld_rlx(&q.ctrl->busy.v);
+            far_ok = bq::bcast64(busy) <= far_gate;
+        }
+        if (e == 0 && far_ok) {
+            // no near work queued or in flight: the home far queue, then the
+            // fullest other one
+            sidx = 2u * a.nseg + home;
+            if (lane == 0) e = bq::ensure_dequeue(fq, (unsigned)B, false, a.bwd != 0);
+            e = bq::bcast32(e);
+            if (e == 0) {
+                long long c = 0;
+                if ((unsigned)lane >= 2u * a.nseg && (unsigned)lane < a.nq &&
+                    (unsigned)lane != 2u * a.nseg + home)
+                    c = bq::ld_rlx((BQ_GLOBAL const long long*)(&(q.ctrl + lane)->count.v));
+                long long best = c > 0 ? c : 0;
+                int who = lane;
+                for (int off = 32; off > 0; off >>= 1) {
+                    const long long ob = __shfl_xor(best, off, 64);
+                    const int ow = __shfl_xor(who, off, 64);
+                    if (ob > best || (ob == best && ow < who)) {
+                        best = ob;
+                        who = ow;
+                    }
+                }
+                if (best > 0) {
+                    sidx = bq::bcast32((unsigned)who);
+                    if (lane == 0)
+                        e = bq::ensure_dequeue(seg_queue(a, sidx), (unsigned)B, true,
+                                               a.bwd != 0);
+                    e = bq::bcast32(e);
+                }
+            }
+        }
         const Queue dq = seg_queue(a, sidx);
         unsigned long long base = 0;
-        if (e && lane == 0) base = bq::add_rlx(&dq.ctrl->head.v, (unsigned long long)e);
+        const bool near_batch = a.bucket_width && e && sidx < 2u * a.nseg;
+        if (e && lane == 0) {
+            if (near_batch) bq::add_rlx(&q.ctrl->busy.v, (unsigned long long)e);
+            base = bq::add_rlx(&dq.ctrl->head.v, (unsigned long long)e);
+        }
         had_work = e > 0 && sidx == home;
         if (e == 0) {
             ++st.idle;
@@ -764,6 +846,21 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
         st.fan += (unsigned long long)fan_total;
         if (lane == 0) L.pre[0] = 0;
         __builtin_amdgcn_wave_barrier();
+        if (sidx >= 2u * a.nseg) {
+            // a far batch: T moves up to its smallest label + the bucket width
+            long long lo = LLONG_MAX;
+            for (unsigned i = lane; i < e; i += 64) lo = L.du[i] < lo ? L.du[i] : lo;
+            for (int off = 32; off > 0; off >>= 1) {
+                const long long o = __shfl_xor(lo, off, 64);
+                lo = o < lo ? o : lo;
+            }
+            if (lane == 0 && lo < LLONG_MAX - bdelta)
+                __hip_atomic_fetch_max((BQ_GLOBAL long long*)&q.ctrl->aux[1].v, lo + bdelta,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // the threshold this batch's pushes are split at
+        const long long tsplit =
+            a.bucket_width ? (long long)bq::bcast64(bq::ld_rlx(&q.ctrl->aux[1].v)) : LLONG_MAX;
 
         // ---- scan the concatenated edge range ---------------------------
         // Three-stage software pipeline over groups of 64*U edges: in each
@@ -856,7 +953,9 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
                 neg |= dropped && cd[r] < lbound;
                 const bool push = won && (old[r] & 1ll) == 0;
                 const unsigned long long pm = bq::ballot(push);
-                if (push) L.out[nout + bq::rank_in(pm)] = (unsigned)tv[r];
+                if (push)
+                    L.out[nout + bq::rank_in(pm)] =
+                        (unsigned)tv[r] | (cd[r] >= tsplit ? FAR_BIT : 0u);
                 nout += __popcll(pm);
             }
             if (__any(neg)) {
@@ -873,7 +972,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
             }
             if (nout > OUTCAP - 64 * U) {
                 __builtin_amdgcn_wave_barrier();
-                if (!flush_vertices(a, hq, cq, L, nout, long_rows, debt, st.spins)) {
+                if (!flush_vertices(a, hq, cq, fq, L, nout, long_rows, debt, st.spins)) {
                     ok = false;
                     break;
                 }
@@ -886,8 +985,11 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
         __builtin_amdgcn_wave_barrier();
         // retire this batch into the debt, then publish the rest
         debt += (long long)e;
-        if (!flush_vertices(a, hq, cq, L, nout, long_rows, debt, st.spins)) break;
+        if (!flush_vertices(a, hq, cq, fq, L, nout, long_rows, debt, st.spins)) break;
         st.push += (unsigned long long)nout;
+        // its pushes are queued: the near batch is no longer in flight
+        if (near_batch && lane == 0)
+            bq::add_rlx(&q.ctrl->busy.v, (unsigned long long)(-(long long)e));
 
         // ---- negative-cycle search once the work looks unbounded --------
         // work so far, estimated from this segment's dequeue position

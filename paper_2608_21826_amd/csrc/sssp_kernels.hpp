@@ -55,6 +55,8 @@ __global__ __launch_bounds__(INIT_WG) void k_init(Queue q, long long* key, int n
     c->error.v = 0ull;
     c->negcycle.v = 0ull;
     c->aux[0].v = (unsigned long long)gridDim.x;  // number of weight-range partials
+    c->aux[1].v = (unsigned long long)LLONG_MIN;  // near / far threshold (buckets)
+    c->busy.v = 0ull;
     for (unsigned sg = 0; sg < MAX_Q; ++sg)        // dequeue positions at start
         q.ctrl[sg].aux[2].v = q.ctrl[sg].head.v;
     c->aux[4].v = bq::now_ticks();                // clock at start

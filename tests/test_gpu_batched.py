@@ -341,3 +341,26 @@ def test_shared_graph_minus_infinity(batch, flags):
         assert flag == neg_ref
         assert np.array_equal(dist.cpu().numpy(), d_ref)
         assert np.array_equal(pred.cpu().numpy(), p_ref)
+
+
+@pytest.mark.parametrize("bw", [1, 4])
+def test_batched_buckets(batch, bw):
+    """Near / far buckets in the batched form: meshes, hubs, shared graphs,
+    a reachable negative cycle and graphs of their own in one launch; every
+    answer must be the oracle's."""
+    mesh = synth.road(64, plant_cycle=False, seed=61)
+    rm = synth.rmat(13, 16, seed=62)
+    cyc = synth.road(20, plant_cycle=True, seed=63)
+    t_mesh, t_rm = upload(mesh), upload(rm)
+    items = [(mesh, int(s), t_mesh) for s in (0, 100, 4095)]
+    items += [(rm, int(s), t_rm) for s in synth.random_sources(rm, 3, seed=64)]
+    items += [(cyc, 0, upload(cyc)), (synth.road(90, seed=65), 7, None),
+              (synth.potential_random(6000, 50000, seed=66), 5, None)]
+    items = [(g, s, t if t is not None else upload(g)) for g, s, t in items]
+    qs, keep = make_queries(items)
+    for graph in (False, True):
+        check_all(qs, keep, batch.solve(qs, launch={"bucket_width": bw}, graph=graph))
+    # a lone large mesh with every queue segment
+    big = synth.road(600, plant_cycle=False, seed=67)
+    qs, keep = make_queries([(big, 0, upload(big))])
+    check_all(qs, keep, batch.solve(qs, launch={"bucket_width": bw, "wg_count": 64}))

@@ -240,6 +240,10 @@ def test_full_size_mix_matches_goldens():
     srv = pkg.Server(4, 32, 8 * road.n, 8 * road.m, 2 << 30)
     for g in resident:
         srv.add_graph(*dev_csr(g))
+    # road2048 requests (large, launched alone) with near / far buckets
+    srv.set_graph_launch(1, {"bucket_width": 1, "wg_count": 64})
+    with pytest.raises(pkg.BQError):
+        srv.set_graph_launch(7, {"bucket_width": 1})
     plan = ([("g", 0, r_rec)] + [("g", 0, q) for q in x_rec["queries"][:8]] +
             [("g", 1, d_rec), ("g", 1, d_rec)] +
             [("g", 2, int(s)) for s in synth.random_sources(er, 4, seed=77)] +

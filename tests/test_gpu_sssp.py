@@ -411,3 +411,63 @@ def test_watchdog_fires_then_context_recovers(ctx, launch):
         ctx.solve(off, col, w, g.src, launch={"timeout_us": 1})
     assert ei.value.status == pkg.BQ_ETIMEOUT
     check(ctx, g, method="fifo")
+
+
+# ---------------------------------------------------------------------------
+# near / far buckets (bucket_width > 0): a different order of work, the same
+# results
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("bw", [1, 4, 64])
+@pytest.mark.parametrize("seed", range(8))
+def test_buckets_random_negative(ctx, bw, seed):
+    rng = np.random.default_rng(5000 + seed)
+    n = int(rng.integers(1, 80))
+    m = int(rng.integers(0, 6 * n + 1))
+    g = synth.random_small(n, m, -6, 30, seed=5100 + seed)
+    check(ctx, g, src=int(rng.integers(0, n)), launch={"bucket_width": bw})
+
+
+@pytest.mark.parametrize("bw", [1, 8])
+@pytest.mark.parametrize("launch", [{}, {"segments": 1}, {"ticket_batch": 4, "wg_count": 32},
+                                    {"flags": pkg.BQ_F_BWD, "segments": 8, "wg_count": 64}],
+                         ids=lambda x: json.dumps(x))
+def test_buckets_meshes_and_hubs(ctx, bw, launch):
+    L = dict(launch, bucket_width=bw)
+    for g in (synth.road(128, plant_cycle=False, seed=5200), synth.rmat(14, 16, seed=5201),
+              synth.potential_random(20000, 160000, seed=5202)):
+        check(ctx, g, launch=L, method="fifo")
+
+
+@pytest.mark.parametrize("cyc_len", [1, 3, 50])
+def test_buckets_negative_cycles_and_marking(ctx, cyc_len):
+    g = synth.road(48, plant_cycle=True, seed=5300 + cyc_len)
+    d, p, neg = run(ctx, g, launch={"bucket_width": 4})
+    assert neg
+    assert check_neg_inf(ctx, g, launch={"bucket_width": 4})
+    rng = np.random.default_rng(cyc_len)
+    n = 400
+    src = rng.integers(0, n, 1600)
+    dst = rng.integers(0, n, 1600)
+    w = rng.integers(1, 50, 1600)
+    cyc = np.arange(100, 100 + cyc_len)
+    s2 = np.concatenate([src, cyc, [0]])
+    d2 = np.concatenate([dst, np.roll(cyc, -1), [100]])
+    w2 = np.concatenate([w, np.full(cyc_len, -1), [5]])
+    g2 = synth.csr_from_edges(n, s2, d2, w2, name="cyc", source=0, meta={})
+    check(ctx, g2, launch={"bucket_width": 1})
+    assert check_neg_inf(ctx, g2, launch={"bucket_width": 1})
+
+
+def test_road2048_buckets_golden(big_ctx):
+    rec = goldens.load("road2048")
+    g = synth.config_graph("road2048")
+    off, col, w = _dev(g)
+    for L in ({"bucket_width": 4}, {"bucket_width": 16, "wg_count": 1024, "segments": 8}):
+        dist, pred, neg = big_ctx.solve(off, col, w, g.src, launch=L)
+        print(f"[sssp] road2048 buckets {L} stats {big_ctx.stats()}", flush=True)
+        assert not neg
+        goldens.check(rec, dist.cpu().numpy(), pred.cpu().numpy(), f"road2048 {L}")
+    g = synth.config_graph("road2048_negcycle")
+    off, col, w = _dev(g)
+    assert big_ctx.solve(off, col, w, g.src, launch={"bucket_width": 4})[2]
