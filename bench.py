@@ -31,6 +31,9 @@ from paper_2608_21826_amd.profsum import kernel_source_hash  # noqa: E402  (no G
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 QUEUE_CAP = 1 << 20
+# RMAT-20 solver launch: the shape sssp_autotune picks most often on MI355X
+# (two-wave workgroups, FIFO order of work, two queue segments)
+RMAT20_LAUNCH = {"wg_count": 192, "segments": 2}
 QUEUE_OPS = 1 << 26
 # algorithmic bytes per unit of work (per dequeued item: row offsets 16 B,
 # key RMW 8 B, slot 4 B, ticket read+write 8 B, queue bookkeeping 4 B; per
@@ -326,6 +329,21 @@ def matches_golden(rec, dist, pred) -> bool:
             sha256(pred.cpu().numpy()) == rec["pred_sha256"])
 
 
+def road_tune(pkg, torch, dev, g):
+    """The library autotuner on the road mesh (it picks near / far buckets
+    there): returns its launch, as a dict of the fields it set."""
+    off = torch.from_numpy(g.offsets).to(dev)
+    col = torch.from_numpy(g.cols).to(dev)
+    w = torch.from_numpy(g.w).to(dev)
+    ctx = pkg.SsspContext(g.n, g.m)
+    try:
+        L, ms = ctx.autotune(off, col, w, g.src, reps=3)
+    finally:
+        ctx.close()
+    log(f"road2048 autotune: {L} {ms:.2f} ms")
+    return {k: v for k, v in L.items() if v}
+
+
 def graph_leg(pkg, torch, dev, name, g, reps, warmup, launch=None, ctx=None):
     """Solves of one configuration at a fixed launch (the library default
     unless given): median device time over `reps` HIP-event-timed solves
@@ -446,23 +464,33 @@ def batched_leg(pkg, torch, dev, name, queries, graphs, steps, single_launch=Non
             **({"parity": parity} if parity is not None else {})}
 
 
-def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0, lanes=4):
+def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0, lanes=4, road_launch=None,
+               pool=20, calib=200):
     """Served form (Poisson arrivals over 3 resident graphs + one-off ER
     uploads): the continuous-batching engine vs the same engine limited to
     one query per launch and one lane (sequential one-query launches), at
-    1.5x and 0.5x the sequential service rate. p50/p99 latency from arrival
-    to completion; GTEPS = reached edges of all requests / wall time."""
+    1.5x and 0.5x the sequential service rate, n_req requests each. 90 % of
+    the requests hit the resident graphs (RMAT-20, road2048, ER-200k), 10 %
+    upload an ER graph drawn from a pool of `pool` graphs with n log-uniform
+    in [1e4, 2e6]. The sequential service rate comes from a closed-loop run
+    of the first `calib` requests of the mix on the sequential engine.
+    Large road2048 requests run with `road_launch` (near / far buckets).
+    p50/p99 latency from arrival to completion; GTEPS = reached edges of all
+    requests / wall time."""
     rng = np.random.default_rng(synth.SEED_BASE + 4 + seed)
     road = synth.config_graph("road2048")
     er = synth.config_graph("er200k")
     resident = [g_rmat, road, er]
     dev_csr = [t_rmat] + [(torch.from_numpy(x.offsets).to(dev), torch.from_numpy(x.cols).to(dev),
                            torch.from_numpy(x.w).to(dev)) for x in (road, er)]
-    up_sizes = np.rint(np.exp(rng.uniform(np.log(1e4), np.log(2e6), size=4))).astype(int)
+    up_sizes = np.rint(np.exp(rng.uniform(np.log(1e4), np.log(2e6), size=pool))).astype(int)
+    t0 = time.time()
     uploads = [synth.erdos_renyi(int(nv), 8, seed=synth.SEED_BASE + 40 + i)
                for i, nv in enumerate(up_sizes)]
     pinned = [(torch.from_numpy(x.offsets).pin_memory(), torch.from_numpy(x.cols).pin_memory(),
                torch.from_numpy(x.w).pin_memory()) for x in uploads]
+    log(f"served: {pool} upload graphs ({int(up_sizes.sum())} vertices) in "
+        f"{time.time() - t0:.1f}s")
     srcs = [synth.random_sources(x, n_req, seed=synth.SEED_BASE + 50 + i)
             for i, x in enumerate(resident)]
     mix = []
@@ -476,9 +504,9 @@ def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0, lanes=4):
     max_n = 8 * max(x.n for x in resident + uploads)
     max_m = 8 * max(x.m for x in resident + uploads)
 
-    def trace(arrivals):
+    def trace(arrivals, count):
         out = []
-        for t, (kind, k, src) in zip(arrivals, mix):
+        for t, (kind, k, src) in zip(arrivals, mix[:count]):
             r = {"arrival_us": float(t), "src": src}
             if kind == "u":
                 r["upload"] = pinned[k]
@@ -489,31 +517,38 @@ def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0, lanes=4):
 
     def run(lanes, max_batch, arrivals):
         srv = pkg.Server(lanes, max_batch, max_n, max_m, 4 << 30)
-        for c in dev_csr:
-            srv.add_graph(*c)
-        srv.run(trace(np.zeros(min(4, n_req))))  # warm-up
-        resp, st = srv.run(trace(arrivals))
-        srv.close()
+        try:
+            for c in dev_csr:
+                srv.add_graph(*c)
+            if road_launch:
+                srv.set_graph_launch(1, road_launch)
+            srv.run(trace(np.zeros(4), 4))  # warm-up
+            resp, st = srv.run(trace(arrivals, len(arrivals)))
+        finally:
+            srv.close()
         lat = np.array([x["latency_us"] for x in resp]) / 1e3
         bad = sum(1 for x in resp if x["status"] != 0)
         edges = sum(x["reached_edges"] for x in resp)
-        return {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+        return {"requests": len(resp), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                 "p99_ms": round(float(np.percentile(lat, 99)), 3),
                 "mean_ms": round(float(lat.mean()), 3), "wall_ms": round(st["wall_ms"], 1),
                 "gteps": round(edges / (st["wall_ms"] * 1e6), 3), "launches": st["launches"],
                 "max_lanes_busy": st["max_lanes_busy"], "max_inflight": st["max_inflight"],
                 "failed": bad}
 
-    # sequential service time (closed loop: everything queued at t=0)
-    seq0 = run(1, 1, np.zeros(n_req))
-    mean_service_ms = seq0["wall_ms"] / n_req
-    res = {"requests": n_req, "mean_sequential_service_ms": round(mean_service_ms, 3)}
+    # sequential service time (closed loop: the first `calib` requests queued at t=0)
+    seq0 = run(1, 1, np.zeros(min(calib, n_req)))
+    mean_service_ms = seq0["wall_ms"] / seq0["requests"]
+    res = {"requests": n_req, "upload_pool": pool, "calibration_requests": seq0["requests"],
+           "mean_sequential_service_ms": round(mean_service_ms, 3),
+           "road2048_launch": road_launch}
     for load in (1.5, 0.5):
         qps = load * 1e3 / mean_service_ms
         arr = np.cumsum(rng.exponential(1e6 / qps, size=n_req))
         res[f"qps_{load}x"] = {"qps": round(qps, 2),
                                "continuous_batching": run(lanes, 32, arr),
                                "sequential": run(1, 1, arr)}
+        log(f"served {load}x: {res[f'qps_{load}x']}")
     return res
 
 
@@ -642,6 +677,9 @@ def main():
                     help='fixed queue launch as JSON, e.g. {"ticket_batch":64,"wg_size":1024}')
     ap.add_argument("--no-tune", action="store_true",
                     help="library default launch shapes (no autotuning)")
+    ap.add_argument("--tune", action="store_true",
+                    help="time the RMAT-20 solve at the autotuner's pick on this box instead "
+                         "of the fixed launch")
     ap.add_argument("--sssp-only", action="store_true",
                     help="skip every leg but the timed RMAT-20 solves (counter passes)")
     ap.add_argument("--queue-only", action="store_true",
@@ -650,7 +688,7 @@ def main():
                     help="skip the batched-vs-one-at-a-time legs")
     ap.add_argument("--no-graphs", action="store_true",
                     help="skip the grid and road legs")
-    ap.add_argument("--served-requests", type=int, default=100,
+    ap.add_argument("--served-requests", type=int, default=2000,
                     help="requests per served run (0 skips the served leg)")
     ap.add_argument("--served-lanes", type=int, default=4,
                     help="lanes of the continuous-batching engine in the served leg")
@@ -757,11 +795,17 @@ def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed
     # launch shapes, chosen before the timed region: the library's autotuner
     # for the solver, a small search over ticket batch / grid for the queue
     sssp_launch = {}
+    tuned = None
     if args.sssp_launch:
         sssp_launch = json.loads(args.sssp_launch)
     elif not args.no_tune and not args.queue_only:
-        sssp_launch, tune_ms = ctx.autotune(off, col, w, g.src, reps=5)
-        log(f"sssp autotune: {sssp_launch} {tune_ms:.3f} ms")
+        # the autotuner's pick varies between near-equal shapes from run to
+        # run; the timed solve uses a fixed launch from repeated tuning runs
+        # (so that the committed kernel profiles are of the timed shape)
+        # unless --tune asks for this run's pick
+        tuned, tune_ms = ctx.autotune(off, col, w, g.src, reps=5)
+        log(f"sssp autotune: {tuned} {tune_ms:.3f} ms")
+        sssp_launch = tuned if args.tune or args.scale != 20 else dict(RMAT20_LAUNCH)
     queue_launch = {"ticket_batch": 1}
     queue_b1_ms = None
     if args.queue_launch:
@@ -863,7 +907,8 @@ def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed
         push = float(np.mean([x["pushes"] for x in ss]))
         alg_bytes = BYTES_PER_DEQ * deq + BYTES_PER_EDGE * rel + BYTES_PER_PUSH * push
         achieved = alg_bytes / (k_ms.mean() * 1e-3) / 1e9
-        out["launch"] = {"sssp": sssp_launch, "queue": queue_launch}
+        out["launch"] = {"sssp": sssp_launch, "queue": queue_launch,
+                         "sssp_autotuner_pick": tuned}
         out["sssp"] = {"ms": round(float(s_ms.mean()), 4),
                        "ms_median": round(float(np.median(s_ms)), 4),
                        "solver_kernel_ms": round(float(k_ms.mean()), 4),
@@ -907,6 +952,7 @@ def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed
 
     out["rounds_form"] = rounds_leg(pkg, torch, g, off, col, w, dist, m_reached)
     log(f"rounds form {out['rounds_form']}")
+    road_launch = None
     if not args.no_graphs:
         graphs = {}
         # C0: the 64 x 64 grid (latency-bound: ~126 hops of queue round trips)
@@ -915,11 +961,16 @@ def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed
         log(f"grid64 {graphs['grid64']}")
         # C2 run A: the 2048 x 2048 road mesh; run B: the planted -3 cycle
         road = synth.config_graph("road2048")
-        graphs["road2048"] = graph_leg(pkg, torch, dev, "road2048", road, reps=5, warmup=2)
-        log(f"road2048 {graphs['road2048']}")
+        road_launch = road_tune(pkg, torch, dev, road)
+        graphs["road2048"] = graph_leg(pkg, torch, dev, "road2048", road, reps=10, warmup=2,
+                                       launch=road_launch)
+        graphs["road2048_fifo"] = graph_leg(pkg, torch, dev, "road2048", road, reps=3, warmup=1,
+                                            launch={"wg_count": 1024, "segments": 8})
+        log(f"road2048 {graphs['road2048']}; FIFO order {graphs['road2048_fifo']}")
         del road
         graphs["road2048_negcycle"] = negcycle_leg(pkg, torch, dev,
-                                                   synth.config_graph("road2048_negcycle"))
+                                                   synth.config_graph("road2048_negcycle"),
+                                                   launch=road_launch)
         log(f"road2048_negcycle {graphs['road2048_negcycle']}")
         out["graphs"] = graphs
         parity_ok &= all(v["parity"] == "exact" for v in graphs.values())
@@ -962,8 +1013,14 @@ def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed
         out["batched"] = batched
     if args.served_requests > 0:
         t0 = time.time()
+        # road requests run alone in the batched form (four-wave workgroups):
+        # the tuned single-query grid of two-wave workgroups, halved
+        rl = None
+        if not args.no_graphs and road_launch and road_launch.get("bucket_width"):
+            rl = {"bucket_width": int(road_launch["bucket_width"]),
+                  "wg_count": max(1, int(road_launch.get("wg_count") or 128) // 2)}
         out["served"] = served_leg(pkg, torch, dev, g, (off, col, w), args.served_requests,
-                                   lanes=args.served_lanes)
+                                   lanes=args.served_lanes, road_launch=rl)
         log(f"served leg in {time.time() - t0:.1f}s: {out['served']}")
     out["parity"]["all_checked_legs"] = "exact" if parity_ok else "MISMATCH"
     return out, parity_ok
