@@ -32,8 +32,8 @@ from paper_2608_21826_amd.profsum import kernel_source_hash  # noqa: E402  (no G
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 QUEUE_CAP = 1 << 20
 # RMAT-20 solver launch: the shape sssp_autotune picks most often on MI355X
-# (two-wave workgroups, FIFO order of work, two queue segments)
-RMAT20_LAUNCH = {"wg_count": 192, "segments": 2}
+# (two-wave workgroups, FIFO order of work, four queue segments)
+RMAT20_LAUNCH = {"wg_count": 256, "segments": 4}
 QUEUE_OPS = 1 << 26
 # algorithmic bytes per unit of work (per dequeued item: row offsets 16 B,
 # key RMW 8 B, slot 4 B, ticket read+write 8 B, queue bookkeeping 4 B; per

@@ -257,11 +257,10 @@ __device__ void build_edge_map(LDS& L, unsigned e, int total) {
 // Publish `cnt` items from the wave's LDS buffer `buf` into queue `seg`
 // (Alg. 1 ENQUEUE for all of them at once). The wave's debt (retired items
 // not yet subtracted from pending, wave-uniform) pays for the items first;
-// pending is raised by the rest before any item becomes visible. `release`
-// orders earlier plain stores (the chunk table) before the items. Returns
+// pending is raised by the rest before any item becomes visible. Returns
 // false on abort.
 __device__ bool flush_out(const SolveArgs& a, const Queue& seg, const unsigned* buf, int cnt,
-                          long long& debt, bool release, unsigned long long& spins) {
+                          long long& debt, unsigned long long& spins) {
     const Queue& q = a.q;
     const int lane = bq::lane_id();
     if (cnt == 0) return true;
@@ -291,7 +290,6 @@ __device__ bool flush_out(const SolveArgs& a, const Queue& seg, const unsigned* 
     debt = need > 0 ? 0 : -need;
     base = bq::bcast64(base);
     if (bq::aborted(q)) return false;
-    if (release) bq::fence_release();
     for (int c0 = 0; c0 < cnt; c0 += 64) {
         const int i = c0 + lane;
         if (!bq::put_slots(seg, i < cnt, base + (unsigned long long)i, i < cnt ? buf[i] : 0u,
@@ -309,7 +307,7 @@ __device__ bool flush_vertices(const SolveArgs& a, const Queue& hq, const Queue&
                                const Queue& fq, LDS& L, int cnt, bool route, long long& debt,
                                unsigned long long& spins) {
     if ((!route && !a.bucket_width) || cnt == 0)
-        return flush_out(a, hq, L.out, cnt, debt, false, spins);
+        return flush_out(a, hq, L.out, cnt, debt, spins);
     const int lane = bq::lane_id();
     const long long C = 1ll << a.chunk_log;
     int nl = 0, nh = 0, nf = 0;
@@ -338,9 +336,9 @@ __device__ bool flush_vertices(const SolveArgs& a, const Queue& hq, const Queue&
         nf += __popcll(fm);
     }
     __builtin_amdgcn_wave_barrier();
-    if (!flush_out(a, hq, L.out, nl, debt, false, spins)) return false;
-    if (!flush_out(a, cq, L.hv, nh, debt, false, spins)) return false;
-    return flush_out(a, fq, L.hv + (OUTCAP - nf), nf, debt, false, spins);
+    if (!flush_out(a, hq, L.out, nl, debt, spins)) return false;
+    if (!flush_out(a, cq, L.hv, nh, debt, spins)) return false;
+    return flush_out(a, fq, L.hv + (OUTCAP - nf), nf, debt, spins);
 }
 
 // Give the wave's debt back to pending (before it waits for work).
@@ -612,6 +610,15 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
     const long long bdelta = a.bucket_width * (maxabs > 1 ? maxabs : 1ll);
     const unsigned long long far_gate =
         FAR_GATE_PER_WAVE * gridDim.x * (unsigned long long)(blockDim.x >> 6);
+    // Row-chunk items a wave takes per batch: about eight scan steps' worth
+    // of edges (4096 at U = 8; 32 chunks of 128, 4 of 1024), at most B. A
+    // hub's chunks then spread over more waves instead of a few taking 64
+    // each (8192 edges at C = 128): the expansion of the source's and the
+    // first hubs' rows, a third of an RMAT-20 solve, ran on a handful of
+    // waves (RMAT-20 1.79 -> 1.71 ms, k 2.68 -> 2.47, at 256 workgroups).
+    unsigned chunk_take = (8u * 64u * U) >> clog;
+    if (chunk_take < 1u) chunk_take = 1u;
+    if (chunk_take > (unsigned)B) chunk_take = (unsigned)B;
     const unsigned long long suspect_after = 4ull * (unsigned long long)a.n +
                                              4ull * (unsigned long long)(a.m >> clog) + 4096ull;
     const unsigned long long walk_stride =
@@ -641,7 +648,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
         // empty, the fullest other queue
         unsigned e = 0;
         unsigned sidx = a.nseg + home;
-        if (lane == 0) e = bq::ensure_dequeue(cq, (unsigned)B, false, a.bwd != 0);
+        if (lane == 0) e = bq::ensure_dequeue(cq, chunk_take, false, a.bwd != 0);
         e = bq::bcast32(e);
         if (e == 0) {
             sidx = home;
@@ -666,8 +673,9 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
             }
             if (best > 0) {
                 sidx = bq::bcast32((unsigned)who);
+                const unsigned want = sidx >= a.nseg ? chunk_take : (unsigned)B;
                 if (lane == 0)
-                    e = bq::ensure_dequeue(seg_queue(a, sidx), (unsigned)B, true, a.bwd != 0);
+                    e = bq::ensure_dequeue(seg_queue(a, sidx), want, true, a.bwd != 0);
                 e = bq::bcast32(e);
             }
         }
@@ -744,8 +752,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
         }
         if (!ok) break;
         // chunk items name their row through chunk_owner, written before
-        // the items were published (release fence on that side)
-        if (any_chunk) bq::fence_acquire();
+        // the items were published (see the fan-out below)
         long_rows |= any_chunk;
         if (a.trace && sidx == 0) {  // timeline of the vertex queue (one segment)
             const unsigned long long w0 = base - head0_lane, w1 = w0 + e;
@@ -826,12 +833,20 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
                         const int ou = L.u[owner_item];
                         const long long js = L.eb[owner_item] >> clog;
                         const long long j = js + 1 + (k - L.fanpre[lo]);
-                        a.chunk_owner[j] = (unsigned)ou;
+                        // an agent-scope store, like the slot words: it is
+                        // complete at the device coherence point before the
+                        // chunk items' slot stores are issued (those wait for
+                        // the tail ticket, and one wave's vector memory
+                        // operations retire in issue order), and the taker
+                        // reads it with an agent-scope load that depends on
+                        // the slot's value. (An L2 write-back / invalidate
+                        // fence pair instead cost 5-8 %.)
+                        bq::st_rlx(&a.chunk_owner[j], (unsigned)ou);
                         L.out[lane] = (unsigned)(n + (unsigned)j);
                     }
                     const int cnt_now = (ftot - t0) < 64 ? (ftot - t0) : 64;
                     __builtin_amdgcn_wave_barrier();
-                    if (!flush_out(a, cq, L.out, cnt_now, debt, true, st.spins)) {
+                    if (!flush_out(a, cq, L.out, cnt_now, debt, st.spins)) {
                         ok = false;
                         break;
                     }
@@ -1021,7 +1036,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
                 const int cnt = (KEY_NEG < old && (old & 1ll) == 0) ? 1 : 0;
                 if (lane == 0) L.out[0] = (unsigned)hit;
                 __builtin_amdgcn_wave_barrier();
-                if (!flush_out(a, hq, L.out, cnt, debt, false, st.spins)) break;
+                if (!flush_out(a, hq, L.out, cnt, debt, st.spins)) break;
                 st.push += (unsigned long long)cnt;
             }
         }
