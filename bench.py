@@ -34,6 +34,9 @@ QUEUE_CAP = 1 << 20
 # RMAT-20 solver launch: the shape sssp_autotune picks most often on MI355X
 # (two-wave workgroups, FIFO order of work, four queue segments)
 RMAT20_LAUNCH = {"wg_count": 256, "segments": 4}
+# Global Mixed queue launch: 256 items per ticket (bulk), 1024-lane
+# workgroups, one per CU (the small search below reports its own pick)
+QUEUE_LAUNCH = {"ticket_batch": 256, "wg_size": 1024, "wg_count": 256}
 QUEUE_OPS = 1 << 26
 # algorithmic bytes per unit of work (per dequeued item: row offsets 16 B,
 # key RMW 8 B, slot 4 B, ticket read+write 8 B, queue bookkeeping 4 B; per
@@ -678,8 +681,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="library default launch shapes (no autotuning)")
     ap.add_argument("--tune", action="store_true",
-                    help="time the RMAT-20 solve at the autotuner's pick on this box instead "
-                         "of the fixed launch")
+                    help="time the RMAT-20 solve and the queue at this run's autotuner / "
+                         "search picks instead of the fixed launches")
     ap.add_argument("--sssp-only", action="store_true",
                     help="skip every leg but the timed RMAT-20 solves (counter passes)")
     ap.add_argument("--queue-only", action="store_true",
@@ -806,8 +809,9 @@ def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed
         tuned, tune_ms = ctx.autotune(off, col, w, g.src, reps=5)
         log(f"sssp autotune: {tuned} {tune_ms:.3f} ms")
         sssp_launch = tuned if args.tune or args.scale != 20 else dict(RMAT20_LAUNCH)
-    queue_launch = {"ticket_batch": 1}
+    queue_launch = dict(QUEUE_LAUNCH)
     queue_b1_ms = None
+    queue_search_best = None
     if args.queue_launch:
         queue_launch = json.loads(args.queue_launch)
     elif not args.sssp_only:
@@ -825,8 +829,10 @@ def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed
                     break
             if args.no_tune:
                 break
-        queue_launch = best[1]
-        log(f"queue launch: {queue_launch} {best[0]:.3f} ms (b=1 best {queue_b1_ms:.3f} ms)")
+        queue_search_best = {"launch": best[1], "ms": round(best[0], 4)}
+        queue_launch = best[1] if args.tune else dict(QUEUE_LAUNCH)
+        log(f"queue search: {best[1]} {best[0]:.3f} ms (b=1 best {queue_b1_ms:.3f} ms); "
+            f"timed launch {queue_launch}")
     queue_part = None
     if not only_timed:
         # the partitioned form (one Broker Queue per XCD, Alg. 2's layout)
@@ -894,7 +900,8 @@ def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed
         out["queue_partitioned"] = queue_part
         out["queue"] = {"ms": round(float(q_ms.mean()), 4),
                         "enq_full": int(qs[-1]["enq_full"]),
-                        "deq_empty": int(qs[-1]["deq_empty"]), "launch": queue_launch}
+                        "deq_empty": int(qs[-1]["deq_empty"]), "launch": queue_launch,
+                        "search_best": queue_search_best}
         out["queue_roofline"] = queue_roofline(float(q_ms.mean()), queue_launch, queue_b1_ms,
                                                probes)
     if not args.queue_only:
