@@ -31,9 +31,11 @@ from paper_2608_21826_amd.profsum import kernel_source_hash  # noqa: E402  (no G
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 QUEUE_CAP = 1 << 20
-# RMAT-20 solver launch: the shape sssp_autotune picks most often on MI355X
-# (two-wave workgroups, FIFO order of work, four queue segments)
-RMAT20_LAUNCH = {"wg_count": 256, "segments": 4}
+# RMAT-20 solver launch: the workgroup count and ticket batch sssp_autotune
+# picks most often on MI355X (256 two-wave workgroups, 128 items per
+# dequeue, FIFO order of work), with four queue segments, the best segment
+# count at that shape in alternating runs
+RMAT20_LAUNCH = {"wg_count": 256, "segments": 4, "ticket_batch": 2}
 # Global Mixed queue launch: 256 items per ticket (bulk), 1024-lane
 # workgroups, one per CU (the small search below reports its own pick)
 QUEUE_LAUNCH = {"ticket_batch": 256, "wg_size": 1024, "wg_count": 256}
@@ -52,26 +54,8 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def read_traffic(per_launch_units):
-    """HBM bytes per solver launch from the committed counter summary, or
-    None when it is missing or was taken on other kernel sources."""
-    if not os.path.exists(PMC_FILE):
-        return None
-    rec = {}
-    for line in open(PMC_FILE):
-        if "=" in line and not line.startswith("#"):
-            k, v = line.split("=", 1)
-            rec[k.strip()] = v.strip()
-    if rec.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    try:
-        return float(rec["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
-
-
-L2_FILE = os.path.join(ROOT, "profiles", "l2_hit_rmat20_queue_rounds.txt")
-ATOMICS_FILE = os.path.join(ROOT, "profiles", "atomics_rmat20_queue.txt")
+TCC_FILE = os.path.join(ROOT, "profiles", "sssp_rmat20_tcc.txt")
+QUEUE_PMC_FILE = os.path.join(ROOT, "profiles", "queue_mixed_b256.txt")
 
 
 def read_counter_summary(path, kernel, key):
@@ -88,7 +72,7 @@ def read_counter_summary(path, kernel, key):
             cur = v
         elif cur == kernel:
             rec[k] = v
-    if rec.get("kernel_source_hash") != kernel_source_hash() or key not in rec:
+    if rec.get("kernel_source_hash") != kernel_source_hash(kernel) or key not in rec:
         return None
     try:
         return float(rec[key])
@@ -161,9 +145,12 @@ def queue_roofline(ms, launch, b1_ms, probes):
     one contended word (probe of leader-lane atomicAdds)."""
     b = int(launch.get("ticket_batch", 1))
     bulk = QUEUE_OPS * 12 / (ms * 1e-3) / 1e9
+    traffic = None
+    if launch == QUEUE_LAUNCH:  # the committed counters were taken at this launch
+        traffic = read_counter_summary(QUEUE_PMC_FILE, "k_bench_mixed", "hbm_bytes_per_launch")
     res = {"bulk": {"bound": "hbm", "achieved": round(bulk, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(bulk / HBM_PEAK_GBS, 4),
-                    "algorithmic_bytes": QUEUE_OPS * 12, "ticket_batch": b,
+                    "traffic": traffic, "algorithmic_bytes": QUEUE_OPS * 12, "ticket_batch": b,
                     "kernel": "k_bench_mixed", "kernel_ms": round(ms, 4)}}
     word = None
     if probes:
@@ -925,17 +912,23 @@ def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed
                        "work_ratio_k": round(rel / m_reached, 3),
                        "relax_per_s_G": round(rel / (k_ms.mean() * 1e-3) / 1e9, 3),
                        "grid": int(ss[-1]["grid"])}
+        # the solver kernel's instantiation for this launch (64 * b items
+        # per dequeue); committed counter summaries are per instantiation
+        kname = f"k_solve<{64 * max(1, int(sssp_launch.get('ticket_batch') or 1))}>"
+        # the committed counters were taken at the fixed RMAT-20 launch
+        tcc = TCC_FILE if sssp_launch == RMAT20_LAUNCH else ""
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                           "traffic": read_traffic(None), "kernel": "k_solve<64>",
-                           "l2_hit_rate": read_counter_summary(L2_FILE, "k_solve",
-                                                               "l2_hit_rate"),
+                           "traffic": read_counter_summary(PMC_FILE if tcc else "", kname,
+                                                           "hbm_bytes_per_launch"),
+                           "kernel": kname,
+                           "l2_hit_rate": read_counter_summary(tcc, kname, "l2_hit_rate"),
                            "algorithmic_bytes_per_launch": int(alg_bytes),
                            "kernel_ms": round(float(k_ms.mean()), 4)}
         # atomics the solver kernel issues (counter summary of the same
         # sources), per second of its time, against the measured
         # random-atomicMin rate
-        n_atomics = read_counter_summary(ATOMICS_FILE, "k_solve", "TCC_ATOMIC_sum_mean")
+        n_atomics = read_counter_summary(tcc, kname, "TCC_ATOMIC_sum_mean")
         if n_atomics:
             out["atomic_rate_G"] = round(n_atomics / (k_ms.mean() * 1e-3) / 1e9, 3)
         if probes:

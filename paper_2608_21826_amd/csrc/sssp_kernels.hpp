@@ -22,12 +22,48 @@ __global__ __launch_bounds__(INIT_WG) void k_init(Queue q, long long* key, int n
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
     const long long srckey = pack_key(0, (1u << (shift - 1u)) - 1u, shift);
-    for (long long v = tid; v < n; v += stride) key[v] = (v == src) ? srckey : KEY_INF;
+    // keys in 16-byte stores and weights in 16-byte loads, each after a
+    // scalar head up to 16-byte alignment and with a scalar tail (the
+    // caller's arrays need only their element alignment)
+    {
+        const long long head = (((uintptr_t)key & 15u) && n > 0) ? 1 : 0;
+        const long long n2 = (n - head) >> 1;
+        for (long long v = tid; v < head; v += stride) key[v] = (v == src) ? srckey : KEY_INF;
+        longlong2* k2 = (longlong2*)(key + head);
+        for (long long i = tid; i < n2; i += stride) {
+            const long long v0 = head + 2 * i;
+            longlong2 x;
+            x.x = (v0 == src) ? srckey : KEY_INF;
+            x.y = (v0 + 1 == src) ? srckey : KEY_INF;
+            k2[i] = x;
+        }
+        for (long long v = head + 2 * n2 + tid; v < n; v += stride)
+            key[v] = (v == src) ? srckey : KEY_INF;
+    }
     int lo = INT_MAX, hi = INT_MIN;
-    for (long long e = tid; e < m; e += stride) {
-        const int x = w[e];
-        lo = x < lo ? x : lo;
-        hi = x > hi ? x : hi;
+    {
+        long long wh = (long long)(((16u - ((uintptr_t)w & 15u)) & 15u) >> 2);
+        if (wh > m) wh = m;
+        const long long m4 = (m - wh) >> 2;
+        for (long long e = tid; e < wh; e += stride) {
+            const int x = w[e];
+            lo = x < lo ? x : lo;
+            hi = x > hi ? x : hi;
+        }
+        const int4* w4 = (const int4*)(w + wh);
+        for (long long i = tid; i < m4; i += stride) {
+            const int4 x = w4[i];
+            const int l01 = x.x < x.y ? x.x : x.y, l23 = x.z < x.w ? x.z : x.w;
+            const int h01 = x.x > x.y ? x.x : x.y, h23 = x.z > x.w ? x.z : x.w;
+            const int l = l01 < l23 ? l01 : l23, h = h01 > h23 ? h01 : h23;
+            lo = l < lo ? l : lo;
+            hi = h > hi ? h : hi;
+        }
+        for (long long e = wh + 4 * m4 + tid; e < m; e += stride) {
+            const int x = w[e];
+            lo = x < lo ? x : lo;
+            hi = x > hi ? x : hi;
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         const int a2 = __shfl_xor(lo, off, 64), b2 = __shfl_xor(hi, off, 64);

@@ -319,6 +319,8 @@ RMAT_SHAPES = [
     None,
     {"wg_count": 192, "segments": 2},
     {"wg_count": 256, "segments": 4},
+    {"wg_count": 256, "segments": 4, "ticket_batch": 2},
+    {"wg_count": 256, "ticket_batch": 4},
     {"wg_count": 128, "segments": 2, "row_chunk": 64},
     {"wg_count": 216, "segments": 2, "row_chunk": 256},
     {"wg_count": 384, "segments": 8, "ticket_batch": 2},
