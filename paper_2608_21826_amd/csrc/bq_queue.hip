@@ -470,7 +470,9 @@ bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
     if (lseg < 0 || (n_ops / 2) % (1ull << lseg)) return BQ_EINVAL;
     const int S2 = 2 << lseg;  // each segment needs an enqueuer and a dequeuer workgroup
     // co-resident grid: enqueuers spin on Full until dequeuers run, so all
-    // workgroups must be resident together (cooperative launch checks it)
+    // workgroups must be resident together. The grid is clamped to what the
+    // occupancy calculator says fits, as for the persistent solver, and a
+    // wait that never ended would still stop at the watchdog (BQ_ETIMEOUT).
     int per_cu = 0;
     BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bench_mixed, L.wg_size, 0));
     const int max_grid = per_cu * bqh::device_cus();
@@ -495,8 +497,8 @@ bq_status bq_bench_mixed(bq_queue* q, uint64_t n_ops, const bq_launch* launch,
     unsigned ls = (unsigned)lseg;
     void* args[] = {&sl, &ct, &lg, &n_half, &el, &dl, &stats, &lim, &bb, &bwd, &ls};
     BQ_HIP_TRY(hipEventRecord(q->ev0, s));
-    BQ_HIP_TRY(hipLaunchCooperativeKernel((const void*)k_bench_mixed, dim3(grid), dim3(L.wg_size),
-                                          args, 0, s));
+    BQ_HIP_TRY(hipLaunchKernel((const void*)k_bench_mixed, dim3(grid), dim3(L.wg_size), args, 0,
+                               s));
     BQ_HIP_TRY(hipEventRecord(q->ev1, s));
     unsigned long long h[4];
     BQ_HIP_TRY(hipMemcpyAsync(h, q->scratch, sizeof h, hipMemcpyDeviceToHost, s));
