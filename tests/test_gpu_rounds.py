@@ -168,6 +168,22 @@ def test_malformed_csr_rejected(ctx):
     check(ctx, g)
 
 
+@pytest.mark.parametrize("launch", [{}, {"flags": pkg.BQ_F_BWD, "ticket_batch": 4}])
+def test_watchdog_fires_then_context_recovers(ctx, launch):
+    """timeout_us = 1: the rounds of this 256 x 256 mesh (hundreds of them,
+    milliseconds in all) run past the host's deadline of ten wait limits, and
+    waves that wait longer than the limit give up inside the kernel, so the
+    call returns BQ_ETIMEOUT after every issued round has ended through its
+    own bounded waits. The next call on the same context must be exact."""
+    g = synth.road(256, plant_cycle=False, seed=8971)
+    off, col, w = _dev(g)
+    print(f"[rounds] watchdog launch={launch}", flush=True)
+    with pytest.raises(pkg.BQError) as ei:
+        ctx.solve(off, col, w, g.src, launch=dict(launch, timeout_us=1))
+    assert ei.value.status == pkg.BQ_ETIMEOUT
+    check(ctx, g, launch=launch or None)
+
+
 def test_repeated_solves_are_identical(ctx):
     g = synth.rmat(14, 16, seed=3)
     first = run(ctx, g)
