@@ -440,6 +440,7 @@ bq_status sssp_bf(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offsets,
     a.bucket_width = L.bucket_width;
     a.nq = (L.bucket_width > 0 ? 3u : 2u) * (unsigned)nseg;
     a.neginf = (L.flags & BQ_F_NEGINF) ? 1u : 0u;
+    a.fan_bulk = 0u;
     a.tcol = nullptr;
     a.tw = nullptr;
     a.orig = nullptr;
@@ -703,6 +704,7 @@ extern "C" bq_status sssp_bf_noalloc(int32_t n, int64_t m, const int64_t* d_offs
     a.bucket_width = L.bucket_width;
     a.nq = (L.bucket_width > 0 ? 3u : 2u) * (unsigned)nseg;
     a.neginf = (L.flags & BQ_F_NEGINF) ? 1u : 0u;
+    a.fan_bulk = 0u;
     a.tcol = nullptr;
     a.tw = nullptr;
     a.orig = nullptr;

@@ -834,6 +834,7 @@ bq_status sssp_bf_batched_start(sssp_batch* b, int32_t count, const sssp_instanc
         a.nq = qps * nseg;
         a.bucket_width = L.bucket_width;
         a.neginf = (L.flags & BQ_F_NEGINF) ? 1u : 0u;
+        a.fan_bulk = 1u;
         d.dist = (long long*)x.dist;
         d.pred = (int*)x.pred;
         d.orig = i;

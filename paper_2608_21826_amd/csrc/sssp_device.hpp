@@ -145,6 +145,12 @@ struct SolveArgs {
                                   // a threshold T that advances in steps of
                                   // k * max(1, max |w|) (see solve_instance)
     unsigned neginf;              // 1: mark minus infinity instead of stopping
+    unsigned fan_bulk;            // 1: a row's chunk items are published with one
+                                  // reservation per OUTCAP items (the batched
+                                  // form); 0: 64 at a time (one query: publishing
+                                  // a hub's chunks faster gets its row scanned
+                                  // before the labels it spreads have settled,
+                                  // k 2.50 -> 2.64 on RMAT-20)
     // Key layout. Null: vertex v's key is key[v] and queue items are vertex
     // ids. Otherwise (the batched form's degree-class layout of a shared
     // graph) keys and vertex items are key positions: key position t holds
@@ -295,6 +301,54 @@ __device__ bool flush_out(const SolveArgs& a, const Queue& seg, const unsigned* 
         if (!bq::put_slots(seg, i < cnt, base + (unsigned long long)i, i < cnt ? buf[i] : 0u,
                            a.limit, spins))
             return false;
+    }
+    return true;
+}
+
+// Publish cnt (<= OUTCAP) items with one reservation, as flush_out does for
+// 64; the slot words of up to four 64-item slices are read together, so a
+// long fan-out costs about one round trip per 256 items instead of three per
+// 64. A slice with a slot not yet released takes the waiting path.
+__device__ bool flush_many(const SolveArgs& a, const Queue& seg, const unsigned* buf, int cnt,
+                           long long& debt, unsigned long long& spins) {
+    const Queue& q = a.q;
+    const int lane = bq::lane_id();
+    if (cnt == 0) return true;
+    const long long need = (long long)cnt - debt;
+    unsigned long long base = 0;
+    if (lane == 0) {
+        // the same order of pending, count and tail as in flush_out
+        if (need > 0) bq::add_rlx(&q.ctrl->pending.v, (unsigned long long)need);
+        const long long old = bq::add_rlx((BQ_GLOBAL long long*)(&seg.ctrl->count.v),
+                                          (long long)cnt);
+        base = bq::add_rlx(&seg.ctrl->tail.v, (unsigned long long)cnt);
+        if (old + cnt > (long long)seg.N) bq::raise_error(q, bq::ERR_FULL);
+    }
+    debt = need > 0 ? 0 : -need;
+    base = bq::bcast64(base);
+    if (bq::aborted(q)) return false;
+    for (int c0 = 0; c0 < cnt; c0 += 256) {
+        unsigned long long w[4];
+        for (int r = 0; r < 4; ++r) {
+            const int i = c0 + 64 * r + lane;
+            w[r] = i < cnt ? bq::ld_rlx(&seg.slots[(base + (unsigned long long)i) & (seg.N - 1ull)])
+                           : 0ull;
+        }
+        for (int r = 0; r < 4; ++r) {
+            if (c0 + 64 * r >= cnt) break;
+            const int i = c0 + 64 * r + lane;
+            const bool act = i < cnt;
+            const unsigned long long pos = base + (unsigned long long)i;
+            const uint32_t rr = bq::round_of(seg, pos);
+            const bool ready = !act || (uint32_t)(w[r] >> 32) == 2u * rr;
+            if (__all(ready)) {
+                if (act)
+                    bq::st_rlx(&seg.slots[pos & (seg.N - 1ull)],
+                               bq::slot_word(2u * rr + 1u, buf[i]));
+            } else if (!bq::put_slots(seg, act, pos, act ? buf[i] : 0u, a.limit, spins)) {
+                return false;
+            }
+        }
     }
     return true;
 }
@@ -820,6 +874,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
                 L.fanpre[lane + 1] = fincl;
                 if (lane == 0) L.fanpre[0] = 0;
                 __builtin_amdgcn_wave_barrier();
+                int nbuf = 0;  // chunk items in L.out not yet published
                 for (int t0 = 0; t0 < ftot; t0 += 64) {
                     const int k = t0 + lane;
                     // chunk items go through the LDS buffer (at most 64 here)
@@ -842,14 +897,17 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
                         // the slot's value. (An L2 write-back / invalidate
                         // fence pair instead cost 5-8 %.)
                         bq::st_rlx(&a.chunk_owner[j], (unsigned)ou);
-                        L.out[lane] = (unsigned)(n + (unsigned)j);
+                        L.out[nbuf + lane] = (unsigned)(n + (unsigned)j);
                     }
-                    const int cnt_now = (ftot - t0) < 64 ? (ftot - t0) : 64;
+                    nbuf += (ftot - t0) < 64 ? (ftot - t0) : 64;
+                    if (a.fan_bulk && nbuf <= OUTCAP - 64 && t0 + 64 < ftot) continue;
                     __builtin_amdgcn_wave_barrier();
-                    if (!flush_out(a, cq, L.out, cnt_now, debt, st.spins)) {
+                    if (!(a.fan_bulk ? flush_many(a, cq, L.out, nbuf, debt, st.spins)
+                                     : flush_out(a, cq, L.out, nbuf, debt, st.spins))) {
                         ok = false;
                         break;
                     }
+                    nbuf = 0;
                     __builtin_amdgcn_wave_barrier();
                 }
                 fan_total += ftot;
