@@ -93,7 +93,8 @@ typedef struct {
                              vertex whose new label is at or above a threshold
                              T goes to a far queue that waves take only when
                              no near work is queued, and a far batch moves T
-                             to its smallest label + k * max(1, max |w|).
+                             to its smallest label + k * max(1, max |w|) / 16
+                             (at least 1).
                              Same results, fewer relabels on large-diameter
                              graphs; the autotuner tries it. Needs one more
                              queue per segment. Other calls ignore it. */
@@ -312,7 +313,8 @@ bq_status sssp_bf_noalloc(int32_t n, int64_t m, const int64_t* d_offsets, const 
  * ticket batches b = 2, 4 around the
  * fastest count, then row chunks 64 and 256 at the fastest shape, then
  * 1, 2 and 4 queue segments against the default, and with buckets bucket
- * widths 2 and 4; `reps` runs per candidate
+ * widths 1, 2 and 16 against the family's 4 (steps of 1/16, 1/8, 1 and 1/4
+ * of max |w|); `reps` runs per candidate
  * (0 = 5), compared by their median, a candidate replacing the fastest so
  * far only when at least 3 % faster; a winner that differs from the best
  * power-of-two count with default settings is finally run against it,

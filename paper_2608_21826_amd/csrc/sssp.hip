@@ -238,13 +238,15 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
     // near / far buckets. One series of each at the default grid picks the
     // family the rest of the search tunes: on a large-diameter graph the
     // buckets save most relabels, on a power-law graph they only add work.
+    // The bucket family is timed at a step of a quarter of max |w|.
+    constexpr int BUCKET_FAMILY_WIDTH = 4;
     if (L.bucket_width == 0) {
         const int g0 = default_grid(n, (long long)m, max_grid);
         std::vector<double> med(2);
         for (int fam = 0; fam < 2; ++fam) {
             bq_launch t = L;
             t.wg_count = g0;
-            t.bucket_width = fam;
+            t.bucket_width = fam ? BUCKET_FAMILY_WIDTH : 0;
             std::vector<double> ts;
             for (int r = 0; r < (reps < 3 ? reps : 3); ++r) {
                 int32_t neg = 0;
@@ -257,7 +259,7 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
             med[fam] = ts[ts.size() / 2];
         }
         if (med[1] < 0.8 * med[0]) {
-            L.bucket_width = 1;
+            L.bucket_width = BUCKET_FAMILY_WIDTH;
             bestL = L;
         }
     }
@@ -313,11 +315,11 @@ bq_status sssp_autotune(sssp_ctx* c, int32_t n, int64_t m, const int64_t* d_offs
             if (st != BQ_OK) return st;
         }
     }
-    // bucket widths 2 and 4 (threshold steps of 2 or 4 max |w|) at the best
-    // shape, for the bucket family
+    // other bucket widths at the best shape, for the bucket family:
+    // threshold steps of 1/16, 1/8 and 1 max |w|
     if (bestL.bucket_width > 0) {
         const bq_launch cur = bestL;
-        for (int bw : {2, 4}) {
+        for (int bw : {1, 2, 16}) {
             L.bucket_width = bw;
             double ms = 0;
             bq_status st = trial(cur.wg_count, cur.ticket_batch, &ms, cur.row_chunk, cur.segments);

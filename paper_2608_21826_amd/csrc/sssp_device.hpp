@@ -143,7 +143,7 @@ struct SolveArgs {
     unsigned nq;                  // queues in use: 2 nseg, or 3 nseg with buckets
     long long bucket_width;       // 0: one FIFO per home; k > 0: near / far split at
                                   // a threshold T that advances in steps of
-                                  // k * max(1, max |w|) (see solve_instance)
+                                  // k * max(1, max |w|) / 16 (see solve_instance)
     unsigned neginf;              // 1: mark minus infinity instead of stopping
     unsigned fan_bulk;            // 1: a row's chunk items are published with one
                                   // reservation per OUTCAP items (the batched
@@ -658,10 +658,11 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
     // others to the far queue. Waves take far work only when no vertex or
     // chunk queue has items and few near items are in flight (the `busy`
     // word); the smallest label of a far batch then moves T up to that
-    // label + k * max(1, max |w|). Processing roughly in label order cuts
-    // the relabels of large-diameter graphs; the order of work never
-    // changes the result.
-    const long long bdelta = a.bucket_width * (maxabs > 1 ? maxabs : 1ll);
+    // label + k * max(1, max |w|) / 16 (at least 1). Processing roughly in
+    // label order cuts the relabels of large-diameter graphs; the order of
+    // work never changes the result.
+    long long bdelta = a.bucket_width * (maxabs > 1 ? maxabs : 1ll) / 16;
+    if (bdelta < 1) bdelta = 1;
     const unsigned long long far_gate =
         FAR_GATE_PER_WAVE * gridDim.x * (unsigned long long)(blockDim.x >> 6);
     // Row-chunk items a wave takes per batch: about eight scan steps' worth

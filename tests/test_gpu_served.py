@@ -241,7 +241,7 @@ def test_full_size_mix_matches_goldens():
     for g in resident:
         srv.add_graph(*dev_csr(g))
     # road2048 requests (large, launched alone) with near / far buckets
-    srv.set_graph_launch(1, {"bucket_width": 1, "wg_count": 64})
+    srv.set_graph_launch(1, {"bucket_width": 4, "wg_count": 64})
     with pytest.raises(pkg.BQError):
         srv.set_graph_launch(7, {"bucket_width": 1})
     plan = ([("g", 0, r_rec)] + [("g", 0, q) for q in x_rec["queries"][:8]] +
