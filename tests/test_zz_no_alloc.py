@@ -35,7 +35,8 @@ def both(g, launch=None):
 
 
 @pytest.mark.parametrize("launch", [None, {"segments": 1, "ticket_batch": 4},
-                                    {"wg_count": 64, "flags": pkg.BQ_F_BWD}])
+                                    {"wg_count": 64, "flags": pkg.BQ_F_BWD},
+                                    {"bucket_width": 4, "segments": 2}])
 def test_noalloc_equals_sssp_bf_twice_then_smaller(launch):
     big = synth.erdos_renyi(200_000, 8, seed=synth.SEED_BASE + 4)   # the served ER graph
     small = synth.potential_random(3000, 24000, seed=4242)
