@@ -919,20 +919,24 @@ def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed
         # the solver kernel's instantiation for this launch (64 * b items
         # per dequeue); committed counter summaries are per instantiation
         kname = f"k_solve<{64 * max(1, int(sssp_launch.get('ticket_batch') or 1))}>"
-        # the committed counters were taken at the fixed RMAT-20 launch
-        tcc = TCC_FILE if sssp_launch == RMAT20_LAUNCH else ""
+
+        def counter(path, key):
+            # the committed counters were taken at the fixed RMAT-20 launch
+            if sssp_launch != RMAT20_LAUNCH:
+                return None
+            return read_counter_summary(path, kname, key)
+
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                           "traffic": read_counter_summary(PMC_FILE if tcc else "", kname,
-                                                           "hbm_bytes_per_launch"),
+                           "traffic": counter(PMC_FILE, "hbm_bytes_per_launch"),
                            "kernel": kname,
-                           "l2_hit_rate": read_counter_summary(tcc, kname, "l2_hit_rate"),
+                           "l2_hit_rate": counter(TCC_FILE, "l2_hit_rate"),
                            "algorithmic_bytes_per_launch": int(alg_bytes),
                            "kernel_ms": round(float(k_ms.mean()), 4)}
         # atomics the solver kernel issues (counter summary of the same
         # sources), per second of its time, against the measured
         # random-atomicMin rate
-        n_atomics = read_counter_summary(tcc, kname, "TCC_ATOMIC_sum_mean")
+        n_atomics = counter(TCC_FILE, "TCC_ATOMIC_sum_mean")
         if n_atomics:
             out["atomic_rate_G"] = round(n_atomics / (k_ms.mean() * 1e-3) / 1e9, 3)
         if probes:
