@@ -885,7 +885,8 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
                 int nbuf = 0;  // chunk items in L.out not yet published
                 for (int t0 = 0; t0 < ftot; t0 += 64) {
                     const int k = t0 + lane;
-                    // chunk items go through the LDS buffer (at most 64 here)
+                    // chunk items go through the LDS buffer, 64 per pass
+                    // (with fan_bulk, up to OUTCAP before they are published)
                     if (k < ftot) {
                         int lo = 0, hi = 64;
                         while (hi - lo > 1) {

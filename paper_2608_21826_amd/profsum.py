@@ -21,6 +21,7 @@ from __future__ import annotations
 import collections
 import hashlib
 import os
+import re
 import sqlite3
 import sys
 
@@ -35,14 +36,24 @@ SOURCES_OF = {  # kernel-name substring -> the sources its code comes from
 }
 
 
+def _code_of(text: str) -> str:
+    """The code of a C++ source without its comments and with its blank
+    space collapsed: editing a comment does not change what a summary
+    describes."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash(kernel: str = "k_solve") -> str:
-    """Hash of the sources a kernel is built from (the single-query solver's
-    by default); a counter summary taken on other sources no longer
-    describes it."""
+    """Hash of the code of the sources a kernel is built from (the
+    single-query solver's by default); a counter summary taken on other code
+    no longer describes it."""
     files = next((v for k, v in SOURCES_OF.items() if k in kernel), KERNEL_SOURCES)
     h = hashlib.sha256()
     for f in files:
-        h.update(open(os.path.join(HERE, "csrc", f), "rb").read())
+        with open(os.path.join(HERE, "csrc", f)) as fh:
+            h.update(_code_of(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
