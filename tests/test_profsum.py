@@ -72,3 +72,12 @@ def test_source_hashes_follow_the_kernel():
     h = profsum.kernel_source_hash
     assert h() == h("k_solve<128>") == h("k_solve<64>")
     assert len({h(), h("k_bsolve"), h("k_bench_mixed")}) == 3
+
+
+def test_source_hash_ignores_comments_not_code():
+    code = profsum._code_of
+    a = "int f(int x) {  // doubles\n  return 2 * x; /* the\n value */ }\n"
+    b = "int f(int x) {\n    return 2 * x;\n}\n"
+    c = "int f(int x) { return 3 * x; }"
+    assert code(a) == code(b)
+    assert code(a) != code(c)
