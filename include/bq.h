@@ -23,6 +23,8 @@
  *    library keeps no caller pointer after the call returns.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *  - Every call returns a bq_status; outputs are unspecified unless BQ_OK.
+ *    A NULL handle gives BQ_EINVAL before any HIP call, except in the
+ *    *_destroy calls, which accept NULL and return BQ_OK.
  *  - Integer arithmetic only: int32 weights, int64 distances.
  *  - The library never allocates on a solve: queues and workspaces are
  *    allocated by bq_create / sssp_ctx_create and reused.
@@ -202,12 +204,16 @@ bq_status bq_reset(bq_queue* q, void* stream);
  * uint64, overwritten) receives the number of successes. Which values
  * succeed, and their order in the queue, depend on the schedule, except for
  * launch->wg_count = 1 and wg_size = 64 (one wave), which enqueues in array
- * order. launch may be NULL. Synchronous (returns after completion). */
+ * order. launch may be NULL. n = 0 launches nothing and writes 0 to *d_n_ok
+ * (d_vals may then be NULL). BQ_EINVAL for a NULL queue or d_n_ok, a NULL
+ * d_vals with n > 0, or a launch shape the queue cannot take.
+ * Synchronous (returns after completion). */
 bq_status bq_enqueue(bq_queue* q, const int32_t* d_vals, uint64_t n, uint64_t* d_n_ok,
                      const bq_launch* launch, void* stream);
 
 /* DEQUEUE up to n values into d_out[0..*d_n_ok) (compacted; Empty for the
  * rest). With one wave (see bq_enqueue) the values come out in queue order.
+ * Arguments and n = 0 as for bq_enqueue (d_out may be NULL when n = 0).
  * Synchronous. */
 bq_status bq_dequeue(bq_queue* q, int32_t* d_out, uint64_t n, uint64_t* d_n_ok,
                      const bq_launch* launch, void* stream);

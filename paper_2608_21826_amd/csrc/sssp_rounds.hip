@@ -445,7 +445,8 @@ bq_status sssp_rounds_create(int32_t max_n, int64_t max_m, sssp_rounds_ctx** out
 }
 
 bq_status sssp_rounds_destroy(sssp_rounds_ctx* c) {
-    if (!c) return BQ_EINVAL;
+    if (!c) return BQ_OK;
+    (void)hipDeviceSynchronize();
     if (c->slots) (void)hipFree(c->slots);
     if (c->ctrl) (void)hipFree(c->ctrl);
     if (c->esrc) (void)hipFree(c->esrc);

@@ -94,3 +94,20 @@ def test_status_codes_match_the_header():
     assert len(set(vals.values())) == len(vals)
     for k in vals:
         assert pkg.strerror(vals[k]) != "unknown status", k
+
+
+def test_null_handles_are_rejected_on_the_host():
+    """Every entry point called with NULL pointers and zero sizes returns
+    before any HIP call (so this runs without a GPU): the *_destroy calls
+    accept NULL, every other call gives BQ_EINVAL."""
+    import paper_2608_21826_amd as pkg
+    L = pkg.lib()
+    host_only = {"bq_strerror", "bq_device_cus"}
+    for name in pkg.EXPORTS:
+        if name in host_only:
+            continue
+        f = getattr(L, name)
+        args = [None if (t is ctypes.c_void_p or hasattr(t, "contents")) else 0
+                for t in f.argtypes]
+        want = pkg.BQ_OK if name.endswith("_destroy") else pkg.BQ_EINVAL
+        assert f(*args) == want, name

@@ -67,6 +67,35 @@ def test_one_wave_matches_sequential_fifo(cap, seed, b, flags):
     q.close()
 
 
+def test_zero_size_calls_change_nothing():
+    """n = 0 enqueues and dequeues (NULL data pointers) report 0 successes and
+    leave the counters alone, on an empty and on a non-empty queue; a dequeue
+    from the drained queue is Empty for every position and moves no head."""
+    print("[queue] zero-size calls", flush=True)
+    L = pkg.lib()
+    q = pkg.Queue(64)
+    ok = torch.full((1,), 7, dtype=torch.int64, device="cuda")
+
+    def zero_calls():
+        for f in (L.bq_enqueue, L.bq_dequeue):
+            ok.fill_(7)
+            st = f(q.handle, None, 0, pkg._ptr(ok), None, pkg._stream())
+            assert st == pkg.BQ_OK and int(ok.item()) == 0
+
+    zero_calls()
+    assert q.counters() == (0, 0, 0)
+    vals = torch.arange(100, 110, dtype=torch.int32, device="cuda")
+    assert q.enqueue(vals, launch=ONE_WAVE) == 10
+    zero_calls()
+    assert q.counters() == (0, 10, 10)
+    out = q.dequeue(20, launch=ONE_WAVE)
+    assert torch.equal(out.cpu(), vals.cpu())
+    assert q.counters() == (10, 10, 0)
+    assert q.dequeue(5).numel() == 0
+    assert q.counters() == (10, 10, 0)
+    q.close()
+
+
 @pytest.mark.parametrize("cap", [64, 4096, 1 << 16])
 @pytest.mark.parametrize("bwd", [False, True])
 def test_many_waves_counts_and_conservation(cap, bwd):
