@@ -295,7 +295,7 @@ def golden(name):
     an independent algorithm)."""
     fname = {"grid64": "grid64.json", "rmat20": "rmat20.json",
              "rmat20_x64_sources": "rmat20.json", "road2048": "road2048.json",
-             "road2048_negcycle": "road2048.json"}[name]
+             "road2048_negcycle": "road2048.json", "er256": "er256.json"}[name]
     with open(os.path.join(GOLDEN_DIR, fname)) as f:
         return json.load(f)[name]
 
@@ -1015,7 +1015,19 @@ def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed
                             torch.empty(eg.n, dtype=torch.int64, device=dev),
                             torch.empty(eg.n, dtype=torch.int32, device=dev)))
             blaunch = json.loads(args.batched_launch) if args.batched_launch else None
-            batched["er256"] = batched_leg(pkg, torch, dev, "er256", bqs, ers, 5, None, blaunch)
+            ge = golden("er256")["queries"]
+            assert all(graph_sha256(eg) == r["graph_sha256"] and eg.src == r["src"]
+                       for eg, r in zip(ers, ge)), "er256: generator output changed"
+
+            def check_er(queries):
+                # all 256 batched answers against the stored results
+                ok = all(matches_golden(r, d_, p_)
+                         for (_, _, _, _, d_, p_), r in zip(queries, ge))
+                return "exact (all 256 queries)" if ok else "MISMATCH"
+
+            batched["er256"] = batched_leg(pkg, torch, dev, "er256", bqs, ers, 5, None, blaunch,
+                                           check=check_er)
+            parity_ok &= batched["er256"]["parity"].startswith("exact")
             log(f"batched er256 {batched['er256']}")
             del bqs, ers
         out["batched"] = batched

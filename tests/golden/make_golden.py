@@ -5,7 +5,8 @@ the smallest-id tight predecessor) on graphs from the seeded generators.
 Before anything is written, every result is certified by an algorithm that
 shares nothing with the oracle:
 
-- potential-shifted graphs (RMAT-20, road2048, their sources): the Johnson
+- potential-shifted graphs (RMAT-20, road2048, the 256 Erdos-Renyi
+  instances of the batched workload, their sources): the Johnson
   closed form. With w = w0 + p(u) - p(v) and w0 >= 1, every path P from s
   to v weighs w0(P) + p(s) - p(v), so d(v) = d0(v) + p(s) - p(v) where d0
   comes from a library Dijkstra (scipy) on the non-negative w0;
@@ -187,6 +188,19 @@ def rmat_golden():
                                    "queries": batch}}
 
 
+def er_golden():
+    """The 256 Erdos-Renyi instances of the batched workload, each from its
+    own source (a small sample of values per instance: the digests carry the
+    exactness)."""
+    queries = []
+    for g in synth.er_batch(256):
+        rec = solve_record(g, g.src, johnson(g, [g.src])[0], samples=16)
+        rec.update({"n": g.n, "m": g.m, "graph_sha256": graph_digest(g)})
+        queries.append(rec)
+    return {"er256": {"count": len(queries), "certified_by": "johnson_closed_form",
+                      "queries": queries}}
+
+
 def grid_golden():
     g = synth.config_graph("grid64")
     rec = solve_record(g, g.src, dijkstra(g, g.src), samples=256)
@@ -196,12 +210,13 @@ def grid_golden():
 
 
 def main():
-    which = sys.argv[1:] or ["grid", "rmat", "road"]
+    which = sys.argv[1:] or ["grid", "rmat", "road", "er"]
     for name in which:
         print(f"{name} ...", flush=True)
-        res = {"grid": grid_golden, "rmat": rmat_golden, "road": road_golden}[name]()
+        res = {"grid": grid_golden, "rmat": rmat_golden, "road": road_golden,
+               "er": er_golden}[name]()
         path = os.path.join(HERE, {"grid": "grid64.json", "rmat": "rmat20.json",
-                                   "road": "road2048.json"}[name])
+                                   "road": "road2048.json", "er": "er256.json"}[name])
         with open(path, "w") as f:
             json.dump(res, f)
         print(f"wrote {path}", flush=True)

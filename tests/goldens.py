@@ -15,7 +15,8 @@ import numpy as np
 
 HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 FILES = {"grid64": "grid64.json", "rmat20": "rmat20.json", "rmat20_x64_sources": "rmat20.json",
-         "road2048": "road2048.json", "road2048_negcycle": "road2048.json"}
+         "road2048": "road2048.json", "road2048_negcycle": "road2048.json",
+         "er256": "er256.json"}
 
 
 def load(name: str) -> dict:

@@ -47,3 +47,21 @@ def test_road2048_generators_match():
         rec = goldens.load(name)
         assert goldens.graph_digest(g) == rec["graph_sha256"], name
         assert (name == "road2048_negcycle") == rec["neg_cycle"]
+
+
+@pytest.mark.slow
+def test_er256_matches_oracle_and_generator():
+    x = goldens.load("er256")
+    graphs = synth.er_batch(256)
+    assert x["count"] == len(x["queries"]) == len(graphs) == 256
+    for g, q in zip(graphs, x["queries"]):
+        assert goldens.graph_digest(g) == q["graph_sha256"], g.name
+        assert g.src == q["src"] and g.n == q["n"] and g.m == q["m"]
+    # the smallest and the largest instance, recomputed
+    sizes = [g.n for g in graphs]
+    for i in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+        g, q = graphs[i], x["queries"][i]
+        d, p, neg = oracle.sssp(g, g.src, method="fifo")
+        assert not neg
+        goldens.check(q, d, p, g.name)
+        assert q["m_reached"] == int(np.diff(g.offsets)[d != oracle.INF].sum())
