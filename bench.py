@@ -454,8 +454,39 @@ def batched_leg(pkg, torch, dev, name, queries, graphs, steps, single_launch=Non
             **({"parity": parity} if parity is not None else {})}
 
 
+def certify_sssp(torch, off, col, w, src, dist, pred) -> bool:
+    """A shortest-path certificate, checked with tensor ops on the GPU (no
+    oracle): d[src] = 0; no edge from a reached vertex can lower its target
+    (d[v] <= d[u] + w); pred[v] is the smallest u with d[u] + w = d[v], -1 for
+    the source and for unreached vertices; every reached vertex other than the
+    source has such a u. On graphs whose cycles all weigh more than zero (the
+    potential-shifted graphs here: every cycle weighs its w0 >= 1 per edge)
+    the tight edges form no cycle, so following pred from any reached vertex
+    ends at the source along a path of weight d[v]; with the edge condition
+    that makes d the exact distances."""
+    inf = torch.iinfo(torch.int64).max
+    n = off.numel() - 1
+    tails = torch.repeat_interleave(torch.arange(n, device=off.device), torch.diff(off))
+    du = dist[tails]
+    fin = du != inf
+    cand = du[fin] + w[fin].to(torch.int64)
+    heads = col[fin].to(torch.int64)
+    if int(dist[src].item()) != 0 or not bool((dist[heads] <= cand).all().item()):
+        return False
+    tight = dist[heads] == cand
+    best = torch.full((n,), n, dtype=torch.int64, device=off.device)
+    best.scatter_reduce_(0, heads[tight], tails[fin][tight], reduce="amin")
+    want = torch.where(best == n, torch.full_like(best, -1), best)
+    want[src] = -1
+    reached = dist != inf
+    want[~reached] = -1
+    if int((want[reached] >= 0).sum().item()) != int(reached.sum().item()) - 1:
+        return False
+    return bool(torch.equal(pred.to(torch.int64), want))
+
+
 def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0, lanes=4, road_launch=None,
-               pool=20, calib=200):
+               pool=20, calib=200, check_n=200):
     """Served form (Poisson arrivals over 3 resident graphs + one-off ER
     uploads): the continuous-batching engine vs the same engine limited to
     one query per launch and one lane (sequential one-query launches), at
@@ -466,7 +497,9 @@ def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0, lanes=4, road_lau
     of the first `calib` requests of the mix on the sequential engine.
     Large road2048 requests run with `road_launch` (near / far buckets).
     p50/p99 latency from arrival to completion; GTEPS = reached edges of all
-    requests / wall time."""
+    requests / wall time. After the timed runs, the first `check_n` requests
+    of the mix run again on the continuous-batching engine into caller
+    buffers, and every answer is checked with `certify_sssp`."""
     rng = np.random.default_rng(synth.SEED_BASE + 4 + seed)
     road = synth.config_graph("road2048")
     er = synth.config_graph("er200k")
@@ -539,6 +572,40 @@ def served_leg(pkg, torch, dev, g_rmat, t_rmat, n_req, seed=0, lanes=4, road_lau
                                "continuous_batching": run(lanes, 32, arr),
                                "sequential": run(1, 1, arr)}
         log(f"served {load}x: {res[f'qps_{load}x']}")
+    # the engine's answers: the head of the mix again, at 1.5x the
+    # sequential rate, into caller buffers, each certified on the GPU
+    count = min(check_n, n_req)
+    reqs = trace(np.cumsum(rng.exponential(mean_service_ms * 1e3 / 1.5, size=count)), count)
+    csr_of = []
+    for r, (kind, k, src) in zip(reqs, mix[:count]):
+        x = uploads[k] if kind == "u" else resident[k]
+        r["dist"] = torch.empty(x.n, dtype=torch.int64, device=dev)
+        r["pred"] = torch.empty(x.n, dtype=torch.int32, device=dev)
+        csr_of.append(("u", k) if kind == "u" else ("g", k))
+    srv = pkg.Server(lanes, 32, max_n, max_m, 4 << 30)
+    try:
+        for c in dev_csr:
+            srv.add_graph(*c)
+        if road_launch:
+            srv.set_graph_launch(1, road_launch)
+        resp, _ = srv.run(reqs)
+    finally:
+        srv.close()
+    up_dev = {}
+    ok = all(x["status"] == 0 and x["neg_cycle"] == 0 for x in resp)
+    for r, (kind, k) in zip(reqs, csr_of):
+        if not ok:
+            break
+        if kind == "g":
+            off_, col_, w_ = dev_csr[k]
+        else:
+            if k not in up_dev:
+                up_dev[k] = tuple(torch.from_numpy(a).to(dev) for a in
+                                  (uploads[k].offsets, uploads[k].cols, uploads[k].w))
+            off_, col_, w_ = up_dev[k]
+        ok = certify_sssp(torch, off_, col_, w_, r["src"], r["dist"], r["pred"])
+    res["parity"] = f"exact (first {count} requests, certified)" if ok else "MISMATCH"
+    log(f"served parity: {res['parity']}")
     return res
 
 
@@ -1042,6 +1109,7 @@ def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed
         out["served"] = served_leg(pkg, torch, dev, g, (off, col, w), args.served_requests,
                                    lanes=args.served_lanes, road_launch=rl)
         log(f"served leg in {time.time() - t0:.1f}s: {out['served']}")
+        parity_ok &= out["served"]["parity"].startswith("exact")
     out["parity"]["all_checked_legs"] = "exact" if parity_ok else "MISMATCH"
     return out, parity_ok
 
