@@ -1030,7 +1030,7 @@ def run_main_legs(args, pkg, torch, dev, g, rec, off, col, w, ctx, q, only_timed
     road_launch = None
     if not args.no_graphs:
         graphs = {}
-        # C0: the 64 x 64 grid (latency-bound: ~126 hops of queue round trips)
+        # C0: the 64 x 64 grid (latency-bound: a shortest-path tree 128 edges deep)
         graphs["grid64"] = graph_leg(pkg, torch, dev, "grid64", synth.config_graph("grid64"),
                                      reps=20, warmup=10, ctx=ctx)
         log(f"grid64 {graphs['grid64']}")
