@@ -830,12 +830,6 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
             }
         }
 
-        // the bucket threshold, read while the batch is staged (the staging
-        // waits for its own loads, so this one costs no round trip of its
-        // own); T only rises, so an early value is a valid split point
-        unsigned long long t_early = 0;
-        if (a.bucket_width && lane == 0) t_early = bq::ld_rlx(&q.ctrl->aux[1].v);
-
         // ---- stage the batch: label, edge range, row chunks --------------
         int carry = 0;
         int fan_total = 0;
@@ -934,8 +928,6 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
         st.fan += (unsigned long long)fan_total;
         if (lane == 0) L.pre[0] = 0;
         __builtin_amdgcn_wave_barrier();
-        // the threshold this batch's pushes are split at
-        long long tsplit = a.bucket_width ? (long long)bq::bcast64(t_early) : LLONG_MAX;
         if (sidx >= 2u * a.nseg) {
             // a far batch: T moves up to its smallest label + the bucket width
             long long lo = LLONG_MAX;
@@ -944,16 +936,13 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
                 const long long o = __shfl_xor(lo, off, 64);
                 lo = o < lo ? o : lo;
             }
-            if (lo < LLONG_MAX - bdelta) {
-                long long prev = 0;
-                if (lane == 0)
-                    prev = __hip_atomic_fetch_max((BQ_GLOBAL long long*)&q.ctrl->aux[1].v,
-                                                  lo + bdelta, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-                prev = (long long)bq::bcast64((unsigned long long)prev);
-                tsplit = prev > lo + bdelta ? prev : lo + bdelta;
-            }
+            if (lane == 0 && lo < LLONG_MAX - bdelta)
+                __hip_atomic_fetch_max((BQ_GLOBAL long long*)&q.ctrl->aux[1].v, lo + bdelta,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        // the threshold this batch's pushes are split at
+        const long long tsplit =
+            a.bucket_width ? (long long)bq::bcast64(bq::ld_rlx(&q.ctrl->aux[1].v)) : LLONG_MAX;
 
         // ---- scan the concatenated edge range ---------------------------
         // Three-stage software pipeline over groups of 64*U edges: in each
