@@ -91,13 +91,38 @@ int default_grid(int n, long long m, int max_grid) {
     return g < max_grid ? g : max_grid;
 }
 
-// co-resident workgroups of k_solve<B> (slot 0, 1, 2 for B = 64, 128, 256)
+// Graphs with fewer than SHORT_ROW_DEGREE edges per vertex on average
+// (meshes, road networks) are solved by the k_solve instantiation that scans
+// SHORT_ROW_UNROLL edges per lane per step instead of U: their batches hold
+// a few hundred edges, one step of either size, and the shorter step issues
+// about half the instructions, which is what a batch cycle on such graphs
+// (a chain of dependent hops) waits for. grid64 1.05-1.06 -> 0.97-0.98 ms,
+// road2048 38.5-38.7 -> 37.7-37.8 ms; RMAT-20 (16 edges per vertex) would
+// need twice the steps and was 12 % slower with it.
+constexpr int SHORT_ROW_UNROLL = 4;
+constexpr long long SHORT_ROW_DEGREE = 6;
+bool short_rows(long long n, long long m) { return m < SHORT_ROW_DEGREE * n; }
+
+// Co-resident workgroups of k_solve<B> and k_solve_short<B> (slot 0, 1, 2
+// for B = 64, 128, 256): the smaller of the two, so that either may be
+// launched on a grid of this size.
+template <int B>
+bq_status occupancy_of_solve(int* per_cu) {
+    int a = 0, b = 0;
+    BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_solve<B>, SOLVE_WG_ONE, 0));
+    BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &b, k_solve_short<B, SHORT_ROW_UNROLL>, SOLVE_WG_ONE, 0));
+    *per_cu = a < b ? a : b;
+    if (*per_cu < 1) *per_cu = 1;
+    return BQ_OK;
+}
+
 template <int B>
 bq_status solve_max_grid(sssp_ctx* c, int slot, int* out) {
     int& per_cu = c->solve_per_cu[slot];
     if (per_cu == 0) {
-        BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<B>, SOLVE_WG_ONE, 0));
-        if (per_cu < 1) per_cu = 1;
+        bq_status st = occupancy_of_solve<B>(&per_cu);
+        if (st != BQ_OK) return st;
     }
     *out = per_cu * bqh::device_cus();
     return BQ_OK;
@@ -112,10 +137,22 @@ bq_status max_grid_for(sssp_ctx* c, int batch, int* out) {
 }
 
 bq_status launch_solve(const SolveArgs& args, int batch, int grid, hipStream_t s) {
+    constexpr int SU = SHORT_ROW_UNROLL;
+    const bool sr = short_rows((long long)args.n, (long long)args.m);
+    const dim3 g(grid), b(SOLVE_WG_ONE);
     switch (batch) {
-        case 1: hipLaunchKernelGGL(k_solve<64>, dim3(grid), dim3(SOLVE_WG_ONE), 0, s, args); break;
-        case 2: hipLaunchKernelGGL(k_solve<128>, dim3(grid), dim3(SOLVE_WG_ONE), 0, s, args); break;
-        default: hipLaunchKernelGGL(k_solve<256>, dim3(grid), dim3(SOLVE_WG_ONE), 0, s, args); break;
+        case 1:
+            if (sr) hipLaunchKernelGGL((k_solve_short<64, SU>), g, b, 0, s, args);
+            else hipLaunchKernelGGL(k_solve<64>, g, b, 0, s, args);
+            break;
+        case 2:
+            if (sr) hipLaunchKernelGGL((k_solve_short<128, SU>), g, b, 0, s, args);
+            else hipLaunchKernelGGL(k_solve<128>, g, b, 0, s, args);
+            break;
+        default:
+            if (sr) hipLaunchKernelGGL((k_solve_short<256, SU>), g, b, 0, s, args);
+            else hipLaunchKernelGGL(k_solve<256>, g, b, 0, s, args);
+            break;
     }
     BQ_HIP_TRY(hipGetLastError());
     return BQ_OK;
@@ -563,21 +600,10 @@ bq_status noalloc_max_grid(int dev, int batch, int* out) {
         per_cu = g_scratch_per_cu[dev][slot];
     }
     if (per_cu == 0) {
-        switch (batch) {
-            case 1:
-                BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<64>,
-                                                                        SOLVE_WG_ONE, 0));
-                break;
-            case 2:
-                BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<128>,
-                                                                        SOLVE_WG_ONE, 0));
-                break;
-            default:
-                BQ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<256>,
-                                                                        SOLVE_WG_ONE, 0));
-                break;
-        }
-        if (per_cu < 1) per_cu = 1;
+        bq_status st = batch == 1 ? occupancy_of_solve<64>(&per_cu)
+                                  : (batch == 2 ? occupancy_of_solve<128>(&per_cu)
+                                                : occupancy_of_solve<256>(&per_cu));
+        if (st != BQ_OK) return st;
         std::lock_guard<std::mutex> lock(g_scratch_mu);
         g_scratch_per_cu[dev][slot] = per_cu;
     }

@@ -603,8 +603,9 @@ __device__ inline void flush_stats(bq::Word* stats, WaveStats& st) {
 // The persistent solver loop of one wave on one query: dequeue a batch,
 // stage it, scan its edges, publish improved vertices; until the query's
 // pending work is 0 (returns 1) or it is stopped (returns -1). The whole
-// workgroup works on the same query; S must be fresh for it.
-template <int B, bool MAP>
+// workgroup works on the same query; S must be fresh for it. UU edges per
+// lane per scan step (U unless the caller picks another).
+template <int B, bool MAP, int UU = U>
 __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& S, int wid,
                               WaveStats& st) {
     const Queue& q = a.q;
@@ -666,12 +667,12 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
     const unsigned long long far_gate =
         FAR_GATE_PER_WAVE * gridDim.x * (unsigned long long)(blockDim.x >> 6);
     // Row-chunk items a wave takes per batch: about eight scan steps' worth
-    // of edges (4096 at U = 8; 32 chunks of 128, 4 of 1024), at most B. A
+    // of edges (4096 at UU = 8; 32 chunks of 128, 4 of 1024), at most B. A
     // hub's chunks then spread over more waves instead of a few taking 64
     // each (8192 edges at C = 128): the expansion of the source's and the
     // first hubs' rows, a third of an RMAT-20 solve, ran on a handful of
     // waves (RMAT-20 1.79 -> 1.71 ms, k 2.68 -> 2.47, at 256 workgroups).
-    unsigned chunk_take = (8u * 64u * U) >> clog;
+    unsigned chunk_take = (8u * 64u * UU) >> clog;
     if (chunk_take < 1u) chunk_take = 1u;
     if (chunk_take > (unsigned)B) chunk_take = (unsigned)B;
     // Parent walks (the negative-cycle search) start once the dequeued work
@@ -945,7 +946,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
             a.bucket_width ? (long long)bq::bcast64(bq::ld_rlx(&q.ctrl->aux[1].v)) : LLONG_MAX;
 
         // ---- scan the concatenated edge range ---------------------------
-        // Three-stage software pipeline over groups of 64*U edges: in each
+        // Three-stage software pipeline over groups of 64*UU edges: in each
         // step the wave issues the atomics of group g, the key loads of group
         // g+1 and the target/weight loads of group g+2, and waits once.
         // An atomicMin is issued only when the candidate is below the key
@@ -959,17 +960,17 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
         // binary search; a batch that fits one step searches (the map would
         // cost more than it saves)
         constexpr int cap = own_cap<B, MAP>();
-        const int mapped = (!MAP || total <= 64 * U) ? 0 : (total < cap ? total : cap);
+        const int mapped = (!MAP || total <= 64 * UU) ? 0 : (total < cap ? total : cap);
         if constexpr (MAP) {
             if (mapped > 0) build_edge_map(L, e, mapped);
         }
         int nout = 0;
-        int av[U], aw[U], aidx[U];           // group g+2: target, weight, item
-        int bv[U], bw[U], bidx[U];           // group g+1
-        long long bkey[U];
+        int av[UU], aw[UU], aidx[UU];           // group g+2: target, weight, item
+        int bv[UU], bw[UU], bidx[UU];           // group g+1
+        long long bkey[UU];
         auto fetch = [&](int t0) {
 #pragma unroll
-            for (int r = 0; r < U; ++r) {
+            for (int r = 0; r < UU; ++r) {
                 const int t = t0 + r * 64 + lane;
                 av[r] = -1;
                 aw[r] = 0;
@@ -985,10 +986,10 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
         };
         // a batch that fits one step skips the key check: there the extra
         // load would only add a round trip
-        const bool check = total > 64 * U;
+        const bool check = total > 64 * UU;
         auto advance = [&]() {  // stage A -> stage B, issuing B's key loads
 #pragma unroll
-            for (int r = 0; r < U; ++r) {
+            for (int r = 0; r < UU; ++r) {
                 bv[r] = av[r];
                 bw[r] = aw[r];
                 bidx[r] = aidx[r];
@@ -998,13 +999,13 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
         };
         fetch(0);
         advance();
-        if (64 * U < total) fetch(64 * U);
-        for (int t0 = 0; t0 < total && ok; t0 += 64 * U) {
-            long long cand[U], cd[U], seen[U];
-            int tv[U];
-            bool valid[U];
+        if (64 * UU < total) fetch(64 * UU);
+        for (int t0 = 0; t0 < total && ok; t0 += 64 * UU) {
+            long long cand[UU], cd[UU], seen[UU];
+            int tv[UU];
+            bool valid[UU];
 #pragma unroll
-            for (int r = 0; r < U; ++r) {
+            for (int r = 0; r < UU; ++r) {
                 tv[r] = bv[r];
                 valid[r] = tv[r] >= 0;
                 seen[r] = bkey[r];
@@ -1015,11 +1016,11 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
                 // proves that a negative cycle reaches the target
                 if (a.neginf && cd[r] < lbound) cand[r] = KEY_NEG;
             }
-            if (t0 + 64 * U < total) advance();
-            if (t0 + 128 * U < total) fetch(t0 + 128 * U);
-            long long old[U];
+            if (t0 + 64 * UU < total) advance();
+            if (t0 + 128 * UU < total) fetch(t0 + 128 * UU);
+            long long old[UU];
 #pragma unroll
-            for (int r = 0; r < U; ++r) {
+            for (int r = 0; r < UU; ++r) {
                 const bool try_it = valid[r] && cand[r] < seen[r];
                 valid[r] = try_it;
                 old[r] = try_it ? __hip_atomic_fetch_min(&a.key[tv[r]], cand[r], __ATOMIC_RELAXED,
@@ -1028,7 +1029,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
             }
             bool neg = false;
 #pragma unroll
-            for (int r = 0; r < U; ++r) {
+            for (int r = 0; r < UU; ++r) {
                 const bool won = valid[r] && cand[r] < old[r];
                 const bool dropped = won && cd[r] < (old[r] >> shift);
                 st.impr += dropped;
@@ -1052,7 +1053,7 @@ __device__ int solve_instance(const SolveArgs& a, WaveLds<B, MAP>& L, WgShared& 
                 if (!flagged && lane == 0) bq::st_rlx(&q.ctrl->negcycle.v, 1ull);
                 flagged = true;
             }
-            if (nout > OUTCAP - 64 * U) {
+            if (nout > OUTCAP - 64 * UU) {
                 __builtin_amdgcn_wave_barrier();
                 if (!flush_vertices(a, hq, cq, fq, L, nout, long_rows, debt, st.spins)) {
                     ok = false;

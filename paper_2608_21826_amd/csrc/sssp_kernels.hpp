@@ -107,8 +107,8 @@ __global__ __launch_bounds__(INIT_WG) void k_init(Queue q, long long* key, int n
     c->count.v = 1ull;
 }
 
-template <int B>
-__global__ __launch_bounds__(SOLVE_WG_ONE, SSSP_MIN_WAVES) void k_solve(SolveArgs a) {
+template <int B, int UU>
+__device__ __forceinline__ void solve_kernel_body(const SolveArgs& a) {
     __shared__ WaveLds<B> lds[WAVES_PER_WG_ONE];
     __shared__ WgShared S;
     WaveLds<B>& L = lds[threadIdx.x >> 6];
@@ -120,8 +120,20 @@ __global__ __launch_bounds__(SOLVE_WG_ONE, SSSP_MIN_WAVES) void k_solve(SolveArg
     }
     __syncthreads();
     WaveStats st{};
-    solve_instance<B>(a, L, S, wid, st);
+    solve_instance<B, true, UU>(a, L, S, wid, st);
     flush_stats(a.q.ctrl->stats, st);
+}
+
+template <int B>
+__global__ __launch_bounds__(SOLVE_WG_ONE, SSSP_MIN_WAVES) void k_solve(SolveArgs a) {
+    solve_kernel_body<B, U>(a);
+}
+
+// the same solver with SHORT_ROW_UNROLL edges per lane per scan step, for
+// graphs whose rows are short on average (see launch_solve)
+template <int B, int UU>
+__global__ __launch_bounds__(SOLVE_WG_ONE, SSSP_MIN_WAVES) void k_solve_short(SolveArgs a) {
+    solve_kernel_body<B, UU>(a);
 }
 
 // dist[v] = d, pred[v] = parent (INT64_MAX / -1 when unreached; pred[src] = -1;
