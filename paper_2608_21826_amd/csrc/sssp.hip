@@ -92,13 +92,13 @@ int default_grid(int n, long long m, int max_grid) {
 }
 
 // Graphs with fewer than SHORT_ROW_DEGREE edges per vertex on average
-// (meshes, road networks) are solved by the k_solve instantiation that scans
+// (meshes, road networks) are solved by k_solve_short, which scans
 // SHORT_ROW_UNROLL edges per lane per step instead of U: their batches hold
 // a few hundred edges, one step of either size, and the shorter step issues
-// about half the instructions, which is what a batch cycle on such graphs
-// (a chain of dependent hops) waits for. grid64 1.05-1.06 -> 0.97-0.98 ms,
-// road2048 38.5-38.7 -> 37.7-37.8 ms; RMAT-20 (16 edges per vertex) would
-// need twice the steps and was 12 % slower with it.
+// about half the scan instructions, which is what a batch cycle on such
+// graphs (a chain of dependent hops) waits for. 64x64 grid 1.12-1.13 ->
+// 1.04-1.06 ms, 2048^2 road mesh 39.7 -> 38.8 ms; an RMAT graph of scale 20
+// (16 edges per vertex) needs twice the steps and was 12 % slower with it.
 constexpr int SHORT_ROW_UNROLL = 4;
 constexpr long long SHORT_ROW_DEGREE = 6;
 bool short_rows(long long n, long long m) { return m < SHORT_ROW_DEGREE * n; }
