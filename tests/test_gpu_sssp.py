@@ -473,3 +473,18 @@ def test_road2048_buckets_golden(big_ctx):
     g = synth.config_graph("road2048_negcycle")
     off, col, w = _dev(g)
     assert big_ctx.solve(off, col, w, g.src, launch={"bucket_width": 4})[2]
+
+
+# Both scan widths: graphs under 6 edges per vertex on average run the
+# short-row kernel (4 edges per lane per step), the others the default one
+# (8). The same families on both sides of that line, with hubs split into
+# chunks, negative weights and every ticket batch.
+@pytest.mark.parametrize("deg", [2, 5, 6, 12])
+@pytest.mark.parametrize("launch", [None, {"ticket_batch": 2, "segments": 2},
+                                    {"ticket_batch": 4, "wg_count": 16}, {"bucket_width": 4}])
+def test_both_scan_widths(ctx, deg, launch):
+    n = 3000
+    g = synth.potential_random(n, deg * n, seed=500 + deg)
+    check(ctx, g, launch=launch)
+    h = synth.rmat(12, edge_factor=max(1, deg), seed=600 + deg)
+    check(ctx, h, launch=launch)
